@@ -1,0 +1,206 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws random relations.  It holds none of the evaluation
+arithmetic, so both the GPU engine's tests and the CPU oracle can take their
+inputs from it without sharing any part of the method.
+
+Every generator uses numpy's counter-based Philox bit generator keyed by an
+integer seed, so a (generator, arguments, seed) triple always yields the same
+relation on every machine.  Relations are returned as ``(n, k)`` C-contiguous
+``uint32`` arrays, one row per tuple, in generation order (not sorted).
+
+Workloads (the paper evaluates on graph and program-analysis relations,
+Sec. 7; its datasets are not available here, so these stand in for their
+shapes):
+
+* ``er_graph``     -- directed G(n, m) over ordered pairs u != v.
+* ``rmat_graph``   -- R-MAT (a, b, c, d) quadrant recursion, hubs at low ids.
+* ``andersen``     -- module-structured points-to input relations.
+* ``batch_sizes``  -- log-uniform instance sizes for batched runs.
+* path / cycle / complete graphs for closed-form checks.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+SEED_BASE = 0x5EED0000
+
+
+def rng(seed: int) -> np.random.Generator:
+    """Philox-keyed generator (seeds up to 128 bits)."""
+    return np.random.Generator(np.random.Philox(key=int(seed)))
+
+
+def _first_distinct(chunks, m: int, key_fn):
+    """Keep the first ``m`` distinct rows, in generation order, from an
+    iterator of row batches.  Raises if the iterator runs dry first."""
+    kept = None
+    kept_keys = None
+    for rows in chunks:
+        keys = key_fn(rows)
+        if kept is None:
+            allrows, allkeys = rows, keys
+        else:
+            allrows = np.concatenate([kept, rows])
+            allkeys = np.concatenate([kept_keys, keys])
+        _, first = np.unique(allkeys, return_index=True)
+        first.sort()
+        kept = allrows[first]
+        kept_keys = allkeys[first]
+        if len(kept) >= m:
+            return np.ascontiguousarray(kept[:m])
+    raise RuntimeError("generator exhausted before reaching the requested size")
+
+
+def _pair_key(rows):
+    return (rows[:, 0].astype(np.uint64) << np.uint64(32)) | rows[:, 1].astype(np.uint64)
+
+
+def er_graph(n: int, m: int, seed: int) -> np.ndarray:
+    """Directed Erdos-Renyi G(n, m): ``m`` distinct ordered pairs (u, v),
+    u != v, drawn uniformly; requires m <= n (n - 1)."""
+    if m > n * (n - 1):
+        raise ValueError("m exceeds the number of ordered pairs")
+    g = rng(seed)
+
+    def batches():
+        while True:
+            b = max(1024, int(m * 1.25) + 64)
+            u = g.integers(0, n, size=b, dtype=np.uint32)
+            v = g.integers(0, n, size=b, dtype=np.uint32)
+            keep = u != v
+            yield np.stack([u[keep], v[keep]], axis=1)
+
+    return _first_distinct(batches(), m, _pair_key)
+
+
+def rmat_graph(scale: int, m: int, seed: int, a=0.57, b=0.19, c=0.19) -> np.ndarray:
+    """R-MAT graph on 2**scale nodes with ``m`` distinct edges, no self-loops.
+
+    Each edge takes ``scale`` independent quadrant draws (probabilities
+    a, b, c, d = 1-a-b-c), building the source and destination bits from the
+    most significant down.  No noise and no vertex relabelling, so the hubs
+    sit at low ids."""
+    g = rng(seed)
+    ab, abc = a + b, a + b + c
+
+    def batches():
+        while True:
+            bsz = max(4096, min(int(m * 0.6) + 64, 1 << 23))
+            src = np.zeros(bsz, dtype=np.uint32)
+            dst = np.zeros(bsz, dtype=np.uint32)
+            for _ in range(scale):
+                r = g.random(bsz, dtype=np.float32)
+                sbit = (r >= ab).astype(np.uint32)
+                dbit = (((r >= a) & (r < ab)) | (r >= abc)).astype(np.uint32)
+                src = (src << np.uint32(1)) | sbit
+                dst = (dst << np.uint32(1)) | dbit
+            keep = src != dst
+            yield np.stack([src[keep], dst[keep]], axis=1)
+
+    return _first_distinct(batches(), m, _pair_key)
+
+
+def path_graph(n: int) -> np.ndarray:
+    """Directed path 0 -> 1 -> ... -> n-1."""
+    i = np.arange(n - 1, dtype=np.uint32)
+    return np.stack([i, i + 1], axis=1)
+
+
+def cycle_graph(n: int) -> np.ndarray:
+    """Directed cycle 0 -> 1 -> ... -> n-1 -> 0."""
+    i = np.arange(n, dtype=np.uint32)
+    return np.stack([i, (i + 1) % n], axis=1).astype(np.uint32)
+
+
+def complete_graph(n: int) -> np.ndarray:
+    """Complete digraph K_n without self-loops."""
+    u, v = np.meshgrid(np.arange(n, dtype=np.uint32), np.arange(n, dtype=np.uint32), indexing="ij")
+    keep = u != v
+    return np.ascontiguousarray(np.stack([u[keep], v[keep]], axis=1))
+
+
+# ---------------------------------------------------------------------------
+# Program-analysis-shaped relations (Andersen points-to inputs).
+# ---------------------------------------------------------------------------
+
+ANDERSEN_FULL = dict(n_modules=1000, vars_per_module=1000, heaps_per_module=200,
+                     n_address_of=500_000, n_assign=2_000_000, n_load=500_000,
+                     n_store=500_000, zipf=1.1)
+
+
+def andersen(seed: int, n_modules=1000, vars_per_module=1000, heaps_per_module=200,
+             n_address_of=500_000, n_assign=2_000_000, n_load=500_000,
+             n_store=500_000, zipf=1.1) -> dict:
+    """Module-structured points-to inputs.
+
+    Module k owns variables [k*V, (k+1)*V) and heap sites
+    H0 + [k*Hm, (k+1)*Hm) with H0 = n_modules*V.  Each tuple picks a module by
+    Zipf(``zipf``) popularity over a seeded permutation of the modules; both
+    endpoints are uniform inside that module (var-var relations reject equal
+    endpoints).  Counts are exact numbers of distinct tuples.
+
+    Returns {"addressOf": (v, h), "assign": (v, w), "load": (v, p),
+    "store": (p, w)} as (n, 2) uint32 arrays.
+    """
+    g = rng(seed)
+    V, Hm = vars_per_module, heaps_per_module
+    H0 = n_modules * V
+    perm = g.permutation(n_modules).astype(np.uint64)
+    w = np.arange(1, n_modules + 1, dtype=np.float64) ** (-zipf)
+    cdf = np.cumsum(w / w.sum())
+
+    def pick_modules(size):
+        r = g.random(size)
+        return perm[np.minimum(np.searchsorted(cdf, r, side="right"), n_modules - 1)]
+
+    def rel(count, second_is_heap):
+        def batches():
+            while True:
+                b = max(1024, int(count * 1.3) + 64)
+                mod = pick_modules(b)
+                x = mod * np.uint64(V) + g.integers(0, V, size=b, dtype=np.uint64)
+                if second_is_heap:
+                    y = np.uint64(H0) + mod * np.uint64(Hm) + g.integers(0, Hm, size=b, dtype=np.uint64)
+                    keep = np.ones(b, dtype=bool)
+                else:
+                    y = mod * np.uint64(V) + g.integers(0, V, size=b, dtype=np.uint64)
+                    keep = x != y
+                yield np.stack([x[keep], y[keep]], axis=1).astype(np.uint32)
+
+        return _first_distinct(batches(), count, _pair_key)
+
+    return {
+        "addressOf": rel(n_address_of, True),
+        "assign": rel(n_assign, False),
+        "load": rel(n_load, False),
+        "store": rel(n_store, False),
+    }
+
+
+def andersen_scaled(seed: int, frac: float) -> dict:
+    """The full-size Andersen input scaled by ``frac`` in module count and in
+    every tuple count (module sizes unchanged)."""
+    p = dict(ANDERSEN_FULL)
+    p["n_modules"] = max(1, int(round(p["n_modules"] * frac)))
+    for k in ("n_address_of", "n_assign", "n_load", "n_store"):
+        p[k] = max(1, int(round(p[k] * frac)))
+    return andersen(seed, **p)
+
+
+# ---------------------------------------------------------------------------
+# Batched instances (many small independent graphs).
+# ---------------------------------------------------------------------------
+
+def batch_sizes(count: int, seed: int, lo=50, hi=5000) -> np.ndarray:
+    """Node counts n_i = floor(exp(U[ln lo, ln hi])) for ``count`` instances."""
+    g = rng(seed)
+    return np.floor(np.exp(g.uniform(np.log(lo), np.log(hi), size=count))).astype(np.int64)
+
+
+def batch_instance(config_seed: int, i: int, n: int, out_degree: int = 4) -> np.ndarray:
+    """Instance i of a batch: ER graph with n nodes and out_degree*n edges,
+    seeded with config_seed * 2**32 + i."""
+    m = min(out_degree * n, n * (n - 1))
+    return er_graph(n, m, (int(config_seed) << 32) + i)

@@ -1,0 +1,281 @@
+"""Pins of the CPU oracle against facts fixed by mathematics and by
+independent algorithms (no GPU).  The oracle is what the engine's parity
+tests compare against, so each of its parts is pinned here by something
+other than itself:
+
+* transitive closure: closed forms for paths, cycles and complete graphs;
+  reachability and the per-round delta sizes from BFS distance layers
+  (for linear TC, delta_k holds exactly the pairs whose shortest walk has
+  k+1 edges);
+* triangles: sum of A o A^2, the AGM bound |tri| <= |E|^1.5, brute force;
+* 4-cycles: trace(A^4); 4-cliques over ascending edges: brute force, C(n,4);
+* points-to: an independent worklist solver;
+* semi-naive rounds: equal to naive Jacobi rounds (hash joins) on random
+  programs, and to brute-force least models on tiny domains;
+* closure of the result under one more application of the rules.
+"""
+
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from paper_2604_20073_amd import workloads as W
+from tests.checkers import (Rule, as_sorted_array, bfs_layers, brute_force, naive_rounds,
+                            points_to, render)
+
+TC = "path(x,y) :- edge(x,y).\npath(x,z) :- path(x,y), edge(y,z)."
+TRI = "tri(x,y,z) :- edge(x,y), edge(y,z), edge(x,z)."
+C4 = "c(w,x,y,z) :- e(w,x), e(x,y), e(y,z), e(z,w)."
+Q4 = ("q(w,x,y,z) :- edge(w,x), edge(x,y), edge(w,y), edge(y,z), edge(x,z), edge(w,z), "
+      "w < x, x < y, y < z.")
+ANDERSEN = """pt(v,h) :- addressOf(v,h).
+pt(v,h) :- assign(v,w), pt(w,h).
+pt(v,h) :- load(v,p), pt(p,q), pt(q,h).
+pt(q,h) :- store(p,w), pt(p,q), pt(w,h)."""
+
+
+def run_tc(edges):
+    o, res = oracle.evaluate({"edge": 2, "path": 2}, TC, {"edge": edges})
+    return o, res["path"]
+
+
+# --------------------------------------------------------------------------
+# Transitive closure
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8, 13, 40])
+def test_tc_path_closed_form(n):
+    o, path = run_tc(W.path_graph(n))
+    assert len(path) == n * (n - 1) // 2
+    expect = np.array([(i, j) for i in range(n) for j in range(i + 1, n)], dtype=np.uint32)
+    assert np.array_equal(path, expect)
+    assert o.delta_sizes("path") == list(range(n - 1, 0, -1)) + [0]
+    assert o.rounds == n - 1
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16])
+def test_tc_cycle_closed_form(n):
+    edges = W.cycle_graph(n) if n > 1 else np.array([[0, 0]], dtype=np.uint32)
+    o, path = run_tc(edges)
+    assert len(path) == n * n
+    assert o.delta_sizes("path") == [n] * n + [0]
+    assert o.rounds == n
+
+
+@pytest.mark.parametrize("n", [2, 3, 6])
+def test_tc_complete_closed_form(n):
+    o, path = run_tc(W.complete_graph(n))
+    assert len(path) == n * n
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tc_matches_bfs_layers(seed):
+    n, m = 60, 150 + 30 * seed
+    edges = W.er_graph(n, m, 1000 + seed)
+    o, path = run_tc(edges)
+    dist = bfs_layers(n, edges)
+    xs, ys = np.nonzero(dist)
+    expect = np.stack([xs, ys], axis=1).astype(np.uint32)
+    assert np.array_equal(path, expect)
+    layers = np.bincount(dist[dist > 0].ravel())[1:]
+    assert o.delta_sizes("path") == [int(c) for c in layers] + [0]
+
+
+def test_tc_config0_bfs_and_closure():
+    """The small plain-engine workload (1,000 nodes, 5,000 edges)."""
+    edges = W.er_graph(1000, 5000, W.SEED_BASE + 0)
+    o, path = run_tc(edges)
+    dist = bfs_layers(1000, edges)
+    assert len(path) == int((dist > 0).sum())
+    layers = np.bincount(dist[dist > 0].ravel())[1:]
+    assert o.delta_sizes("path") == [int(c) for c in layers] + [0]
+    # Closure: path o edge is contained in path.
+    P = sp.csr_matrix((np.ones(len(path)), (path[:, 0], path[:, 1])), shape=(1000, 1000))
+    A = sp.csr_matrix((np.ones(len(edges)), (edges[:, 0], edges[:, 1])), shape=(1000, 1000))
+    extra = ((P @ A) > 0).astype(np.int8) - (P > 0).astype(np.int8)
+    assert extra.max() <= 0
+
+
+def test_tc_right_linear_and_nonlinear_agree():
+    edges = W.er_graph(50, 120, 7)
+    _, left = run_tc(edges)
+    for rules in ["path(x,y) :- edge(x,y).\npath(x,z) :- edge(x,y), path(y,z).",
+                  "path(x,y) :- edge(x,y).\npath(x,z) :- path(x,y), path(y,z)."]:
+        _, res = oracle.evaluate({"edge": 2, "path": 2}, rules, {"edge": edges})
+        assert np.array_equal(res["path"], left)
+
+
+# --------------------------------------------------------------------------
+# Triangles, 4-cycles, 4-cliques
+# --------------------------------------------------------------------------
+
+def adjacency(n, edges):
+    return sp.csr_matrix((np.ones(len(edges), dtype=np.int64), (edges[:, 0], edges[:, 1])),
+                         shape=(n, n))
+
+
+@pytest.mark.parametrize("n", [3, 4, 6])
+def test_triangles_complete(n):
+    _, res = oracle.evaluate({"edge": 2, "tri": 3}, TRI, {"edge": W.complete_graph(n)})
+    assert len(res["tri"]) == n * (n - 1) * (n - 2)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_triangles_matrix_count_and_agm(seed):
+    n = 300
+    edges = W.rmat_graph(9, 3000, 50 + seed)
+    _, res = oracle.evaluate({"edge": 2, "tri": 3}, TRI, {"edge": edges})
+    A = adjacency(512, edges)
+    expect = int(A.multiply(A @ A).sum())
+    assert len(res["tri"]) == expect
+    assert len(res["tri"]) <= len(edges) ** 1.5
+    del n
+
+
+def test_triangles_brute_force():
+    edges = W.er_graph(9, 30, 3)
+    _, res = oracle.evaluate({"edge": 2, "tri": 3}, TRI, {"edge": edges})
+    s = set(map(tuple, edges.tolist()))
+    expect = sorted((x, y, z) for x, y, z in itertools.product(range(9), repeat=3)
+                    if (x, y) in s and (y, z) in s and (x, z) in s)
+    assert res["tri"].tolist() == [list(t) for t in expect]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_4cycles_trace(seed):
+    edges = W.er_graph(40, 160, 90 + seed)
+    _, res = oracle.evaluate({"e": 2, "c": 4}, C4, {"e": edges})
+    A = adjacency(40, edges).toarray()
+    assert len(res["c"]) == int(np.trace(np.linalg.matrix_power(A, 4)))
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 8])
+def test_4cliques_complete(n):
+    _, res = oracle.evaluate({"edge": 2, "q": 4}, Q4, {"edge": W.complete_graph(n)})
+    assert len(res["q"]) == math.comb(n, 4)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_4cliques_brute_force(seed):
+    n = 14
+    edges = W.er_graph(n, 110, 200 + seed)
+    _, res = oracle.evaluate({"edge": 2, "q": 4}, Q4, {"edge": edges})
+    s = set(map(tuple, edges.tolist()))
+    expect = [c for c in itertools.combinations(range(n), 4)
+              if all((a, b) in s for a, b in itertools.combinations(c, 2))]
+    assert res["q"].tolist() == [list(t) for t in expect]
+
+
+# --------------------------------------------------------------------------
+# Points-to
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(3))
+def test_andersen_worklist(seed):
+    rel = W.andersen(300 + seed, n_modules=4, vars_per_module=30, heaps_per_module=8,
+                     n_address_of=40, n_assign=100, n_load=30, n_store=30)
+    _, res = oracle.evaluate({"addressOf": 2, "assign": 2, "load": 2, "store": 2, "pt": 2},
+                             ANDERSEN, rel)
+    expect = as_sorted_array(points_to(rel["addressOf"], rel["assign"], rel["load"],
+                                       rel["store"]), 2)
+    assert np.array_equal(res["pt"], expect)
+
+
+def test_andersen_assign_only_is_reachability():
+    rel = W.andersen(9, n_modules=3, vars_per_module=40, heaps_per_module=10,
+                     n_address_of=30, n_assign=90, n_load=1, n_store=1)
+    prog = "pt(v,h) :- addressOf(v,h).\npt(v,h) :- assign(v,w), pt(w,h)."
+    _, res = oracle.evaluate({"addressOf": 2, "assign": 2, "pt": 2}, prog,
+                             {"addressOf": rel["addressOf"], "assign": rel["assign"]})
+    nv = 120
+    reach = bfs_layers(nv, rel["assign"]) > 0
+    np.fill_diagonal(reach, True)
+    expect = set()
+    for v, h in rel["addressOf"].tolist():
+        for u in np.nonzero(reach[:, v])[0]:
+            expect.add((int(u), h))
+    assert np.array_equal(res["pt"], as_sorted_array(expect, 2))
+
+
+# --------------------------------------------------------------------------
+# Semi-naive rounds against naive rounds and brute force
+# --------------------------------------------------------------------------
+
+PROGRAMS = {
+    "tc_left": [Rule(("path", ("x", "y")), [("edge", ("x", "y"))]),
+                Rule(("path", ("x", "z")), [("path", ("x", "y")), ("edge", ("y", "z"))])],
+    "tc_nonlinear": [Rule(("path", ("x", "y")), [("edge", ("x", "y"))]),
+                     Rule(("path", ("x", "z")), [("path", ("x", "y")), ("path", ("y", "z"))])],
+    "same_gen": [Rule(("sg", ("x", "y")), [("edge", ("p", "x")), ("edge", ("p", "y")),
+                                            ], [("!=", "x", "y")]),
+                 Rule(("sg", ("x", "y")), [("edge", ("a", "x")), ("sg", ("a", "b")),
+                                           ("edge", ("b", "y"))])],
+    "mutual": [Rule(("even", ("x", "y")), [("edge", ("x", "y")), ("edge", ("y", "x"))]),
+               Rule(("odd", ("x", "z")), [("even", ("x", "y")), ("edge", ("y", "z"))]),
+               Rule(("even", ("x", "z")), [("odd", ("x", "y")), ("edge", ("y", "z"))]),
+               Rule(("top", ("x",)), [("odd", ("x", "y")), ("even", ("y", "x")),
+                                       ], [("<", "x", "y")])],
+    "consts": [Rule(("r", ("y",)), [("edge", (0, "y"))]),
+               Rule(("r", ("z",)), [("r", ("y",)), ("edge", ("y", "z"))], [("!=", "z", 3)]),
+               Rule(("pair", ("y", 7)), [("r", ("y",)), ("edge", ("y", "y2"))], [("<=", "y", "y2")])],
+    "selfjoin": [Rule(("s", ("x", "x")), [("edge", ("x", "y")), ("edge", ("y", "x"))]),
+                 Rule(("s", ("x", "z")), [("s", ("x", "y")), ("s", ("y", "w")), ("edge", ("w", "z"))])],
+}
+ARITY = {"edge": 2, "path": 2, "sg": 2, "even": 2, "odd": 2, "top": 1, "r": 1, "pair": 2, "s": 2}
+
+
+@pytest.mark.parametrize("name", sorted(PROGRAMS))
+@pytest.mark.parametrize("seed", range(3))
+def test_semi_naive_equals_naive_rounds(name, seed):
+    rules = PROGRAMS[name]
+    names = sorted({r.head[0] for r in rules} | {a[0] for r in rules for a in r.body})
+    edges = W.er_graph(12, 26, 500 + seed)
+    rels = {n: ARITY[n] for n in names}
+    o, res = oracle.evaluate(rels, render(rules), {"edge": edges})
+    model, deltas = naive_rounds(rules, {"edge": edges}, names)
+    for n in names:
+        assert np.array_equal(res[n], as_sorted_array(model[n], ARITY[n])), n
+    for n, d in deltas.items():
+        assert o.delta_sizes(n) == d, n
+
+
+@pytest.mark.parametrize("name", sorted(PROGRAMS))
+def test_least_model_brute_force(name):
+    rules = PROGRAMS[name]
+    names = sorted({r.head[0] for r in rules} | {a[0] for r in rules for a in r.body})
+    edges = W.er_graph(5, 9, 77)
+    rels = {n: ARITY[n] for n in names}
+    _, res = oracle.evaluate(rels, render(rules), {"edge": edges})
+    model = brute_force(rules, {"edge": edges}, names)
+    for n in names:
+        assert np.array_equal(res[n], as_sorted_array(model[n], ARITY[n])), n
+
+
+def test_loaded_facts_in_head_relation_join_delta0():
+    """Facts loaded into a derived relation are part of its first delta."""
+    edges = W.path_graph(5)
+    seed = np.array([[4, 0]], dtype=np.uint32)
+    o, res = oracle.evaluate({"edge": 2, "path": 2}, TC, {"edge": edges, "path": seed})
+    # path(4,0) is not an edge, so it only extends forward: (4,0)..(4,4).
+    assert len(res["path"]) == 10 + 5
+    assert o.delta_sizes("path")[0] == 5
+    rules = PROGRAMS["tc_left"]
+    model, deltas = naive_rounds(rules, {"edge": edges, "path": seed}, ["edge", "path"])
+    assert np.array_equal(res["path"], as_sorted_array(model["path"], 2))
+    assert o.delta_sizes("path") == deltas["path"]
+
+
+def test_rejects_unsafe_and_malformed_rules():
+    o = oracle.Oracle({"edge": 2, "p": 2})
+    with pytest.raises(oracle.OracleError):
+        o.add_rules("p(x,z) :- edge(x,y).")
+    with pytest.raises(oracle.OracleError):
+        o.add_rules("p(x,y) :- edge(x,y), z < x.")
+    with pytest.raises(oracle.OracleError):
+        o.add_rules("p(x) :- edge(x,y).")
+    with pytest.raises(oracle.OracleError):
+        o.add_rules("p(x,y) :- nosuch(x,y).")
