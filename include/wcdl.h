@@ -1,0 +1,284 @@
+/*
+ * wcdl.h -- C ABI of the worst-case-optimal Datalog engine for AMD MI355X.
+ *
+ * The engine evaluates positive Datalog programs (Horn clauses, paper Sec. 2
+ * "Datalog") to their least fixpoint by semi-naive evaluation (Sec. 2, the
+ * differential form of the fixpoint), running every multi-way rule body as a
+ * worst-case-optimal join over flat, sorted, columnar uint32 relations
+ * (Sec. 2 "Join Processing", Sec. 4).  Each iteration follows the staged
+ * pipeline of Sec. 4: Histogram, Count, Scan/allocate, Materialize, Compute
+ * Delta, Build Index, Merge; work is balanced by the root-level histogram of
+ * Sec. 5 (Alg. 1 and Alg. 2).  All of it runs in HIP kernels on one GPU.
+ *
+ * Calls follow the paper's statement of the problem: declare relations with
+ * their arity, load input facts as columns, register rules, run to the
+ * fixpoint, read back derived relations.
+ *
+ * Conventions (every entry point):
+ *  - Return a wcdl_status: 0 on success, a negative WCDL_E_* code on error.
+ *    No C++ exception crosses this boundary.  After an error,
+ *    wcdl_last_error() returns a human-readable message, and the engine is
+ *    still valid unless the code is WCDL_E_DEVICE.
+ *  - One engine is used by one host thread at a time.
+ *  - Calls are synchronous: when a call returns, the device work it issued
+ *    has completed and caller buffers passed to it may be reused.
+ *  - Values are uint32; every uint32 value is a valid datum (no sentinel).
+ *    Comparisons in rules are unsigned 32-bit.
+ *  - Row counts, sizes and offsets are uint64.
+ *  - Relations are sets: loading deduplicates silently; results are always
+ *    returned sorted lexicographically by column 0, 1, ..., arity-1, with no
+ *    duplicate rows.
+ */
+#ifndef WCDL_H
+#define WCDL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t wcdl_status;
+
+#define WCDL_OK 0
+#define WCDL_E_INVALID (-1)       /* null pointer, bad size, bad flag */
+#define WCDL_E_ARITY (-2)         /* atom arity differs from the declaration */
+#define WCDL_E_UNKNOWN_REL (-3)   /* relation id or name not declared */
+#define WCDL_E_UNSAFE_RULE (-4)   /* head/comparison variable not bound by a body atom */
+#define WCDL_E_UNSUPPORTED (-5)   /* exceeds the engine's static limits below */
+#define WCDL_E_STATE (-6)         /* call not allowed in the current state */
+#define WCDL_E_NOMEM (-7)         /* device allocation failed */
+#define WCDL_E_BUDGET (-8)        /* a count-pass bound exceeded mem_budget_bytes */
+#define WCDL_E_DEVICE (-9)        /* HIP runtime error; the engine must be destroyed */
+#define WCDL_E_PARSE (-10)        /* rule text does not parse */
+
+/* Static limits of one rule (after the planner's rewrites). */
+#define WCDL_MAX_ARITY 6
+#define WCDL_MAX_BODY 8
+#define WCDL_MAX_VARS 8
+#define WCDL_MAX_CMPS 8
+
+/* Configuration flags (wcdl_config.flags). */
+#define WCDL_F_BALANCE_OFF 0x1u  /* one root key per workgroup instead of the
+                                    histogram-balanced split of [0,T) (the
+                                    ablation baseline of Sec. 7.3) */
+#define WCDL_F_STREAMS_OFF 0x2u  /* evaluate rule versions one after another on
+                                    one stream (the sequential schedule of
+                                    Sec. 7.4) instead of phase-aligned on
+                                    several streams (Sec. 6) */
+#define WCDL_F_XPROD_OFF 0x4u    /* disable the per-unit decode fast path for
+                                    cross-product plans (Sec. 5, work-unit
+                                    decode); use the general kernel instead */
+
+typedef struct wcdl_engine wcdl_engine;
+
+/* Device memory provider.  alloc returns device memory of at least `bytes`
+ * bytes usable on `stream` (a hipStream_t), or NULL on failure; free releases
+ * a pointer that alloc returned, with the same byte count.  The engine
+ * caches blocks it frees and returns them all at wcdl_destroy.  When alloc is
+ * NULL the engine uses hipMalloc/hipFree. */
+typedef struct {
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* ptr, size_t bytes, void* stream);
+  void* ctx;
+} wcdl_allocator;
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal */
+  uint32_t n_streams;        /* number of entries in `streams`; 0 = engine creates 4 */
+  void* const* streams;      /* hipStream_t handles owned by the caller; stream 0 is
+                                the main stream (all default priority) */
+  wcdl_allocator alloc;      /* see above */
+  uint64_t mem_budget_bytes; /* 0 = unlimited; otherwise a rule version whose
+                                count-pass output would exceed it fails the run
+                                with WCDL_E_BUDGET */
+  uint32_t flags;            /* WCDL_F_* */
+  uint32_t wg_per_cu;        /* work-partition oversubscription: p = 256 CUs x
+                                wg_per_cu workgroups per join; 0 = default (8) */
+} wcdl_config;
+
+/* Fill `cfg` with defaults (device 0, own streams, hipMalloc, no budget). */
+void wcdl_config_default(wcdl_config* cfg);
+
+/* Create an engine on cfg->device.  *out receives the engine. */
+wcdl_status wcdl_create(const wcdl_config* cfg, wcdl_engine** out);
+
+/* Destroy an engine and free every device buffer it holds.  NULL is a no-op. */
+void wcdl_destroy(wcdl_engine* e);
+
+/* Message describing the last error on this engine (never NULL; "" if none).
+ * Valid until the next call on the engine. */
+const char* wcdl_last_error(const wcdl_engine* e);
+
+/* Declare a relation (paper Sec. 2: input and derived relations are both
+ * just relations).  name: [A-Za-z_][A-Za-z0-9_]*, unique; 1 <= arity <=
+ * WCDL_MAX_ARITY.  *rel_id receives its id (dense, from 0). */
+wcdl_status wcdl_declare_relation(wcdl_engine* e, const char* name, uint32_t arity,
+                                  uint32_t* rel_id);
+
+/* Look up a relation id by name. */
+wcdl_status wcdl_relation_id(const wcdl_engine* e, const char* name, uint32_t* rel_id);
+
+/* Add input facts to a relation (Sec. 4: relations are flat structure-of-
+ * arrays columns).  cols[j] points to n_rows uint32 values of column j,
+ * j < arity; on_device != 0 means the pointers are device memory on the
+ * engine's device, else host memory.  The engine copies the data (the caller
+ * keeps ownership) and merges it with facts loaded before; duplicates are
+ * dropped.  Facts may be loaded into relations that rules also derive; they
+ * join the first delta of their stratum.  Allowed before and between runs. */
+wcdl_status wcdl_load_columns(wcdl_engine* e, uint32_t rel, const uint32_t* const* cols,
+                              uint64_t n_rows, int on_device);
+
+/* Remove every loaded fact of a relation (derived facts are recomputed by
+ * the next run). */
+wcdl_status wcdl_clear_relation(wcdl_engine* e, uint32_t rel);
+
+/* ---- Rules as data ---------------------------------------------------- */
+
+#define WCDL_VAR 0u
+#define WCDL_CONST 1u
+typedef struct {
+  uint32_t kind;  /* WCDL_VAR: value is a variable id local to the rule;
+                     WCDL_CONST: value is the constant */
+  uint32_t value;
+} wcdl_term;
+
+typedef struct {
+  uint32_t rel;
+  uint32_t arity;
+  const wcdl_term* terms;
+} wcdl_atom;
+
+#define WCDL_LT 0u /* lhs <  rhs */
+#define WCDL_LE 1u /* lhs <= rhs */
+#define WCDL_NE 2u /* lhs != rhs */
+#define WCDL_GT 3u /* lhs >  rhs */
+#define WCDL_GE 4u /* lhs >= rhs */
+typedef struct {
+  uint32_t op;
+  wcdl_term lhs;
+  wcdl_term rhs;
+} wcdl_cmp;
+
+/* Head(...) <- Body_1(...), ..., Body_n(...), comparisons (Sec. 2).  Every
+ * head and comparison variable must occur in a body atom (safety).
+ * var_order, if not NULL, fixes the join's variable order (n_vars entries,
+ * each body variable exactly once); NULL lets the planner choose (delta
+ * relation outermost, Sec. 7.3). */
+typedef struct {
+  wcdl_atom head;
+  uint32_t n_body;
+  const wcdl_atom* body;
+  uint32_t n_cmp;
+  const wcdl_cmp* cmp;
+  uint32_t n_vars;
+  const uint32_t* var_order;
+} wcdl_rule;
+
+/* Register one rule; *rule_id receives its id.  Rejected with
+ * WCDL_E_UNSAFE_RULE, WCDL_E_ARITY, WCDL_E_UNKNOWN_REL or
+ * WCDL_E_UNSUPPORTED (limits above). */
+wcdl_status wcdl_add_rule(wcdl_engine* e, const wcdl_rule* rule, uint32_t* rule_id);
+
+/* Register rules from text, e.g.
+ *   "path(x,y) :- edge(x,y).  path(x,z) :- path(x,y), edge(y,z), x != z."
+ * Identifiers in argument position are variables ("_" is anonymous),
+ * decimal numbers are constants, comparisons are < <= > >= !=, and '%' or
+ * '//' starts a comment.  Relations must be declared first.  A ground clause
+ * without a body adds a fact.  All-or-nothing: on error no rule is added. */
+wcdl_status wcdl_add_rules_text(wcdl_engine* e, const char* text);
+
+/* Number of registered rules (helper rules from wcdl_split_rule included). */
+wcdl_status wcdl_rule_count(const wcdl_engine* e, uint32_t* n);
+
+/* Helper-relation splitting (Sec. 5, the CallGraphEdge rewrite): factor the
+ * body atoms atom_idx[0..n) of rule rule_id into a new relation whose columns
+ * are the variables those atoms share with the rest of the rule (other
+ * atoms, head, comparisons), in order of first occurrence.  The rule becomes
+ * head <- remaining atoms, helper(shared...) and a new rule
+ * helper(shared...) <- selected atoms is added.  The least model of every
+ * previously declared relation is unchanged.  *helper_rel receives the new
+ * relation's id (named "<head>__h<k>"). */
+wcdl_status wcdl_split_rule(wcdl_engine* e, uint32_t rule_id, const uint32_t* atom_idx,
+                            uint32_t n, uint32_t* helper_rel);
+
+/* ---- Evaluation ------------------------------------------------------- */
+
+/* Phase indices of wcdl_run_stats.phase_ms (device time, summed over rounds). */
+#define WCDL_PH_HISTOGRAM 0   /* root-key histogram and its prefix sum (Alg. 1 Ph. 1) */
+#define WCDL_PH_COUNT 1       /* count kernels + offset scan (Alg. 1 Ph. 2) */
+#define WCDL_PH_MATERIALIZE 2 /* materialize kernels (Alg. 1 Ph. 3) */
+#define WCDL_PH_DELTA 3       /* sort, dedup, difference against the full relation */
+#define WCDL_PH_INDEX 4       /* sorting the delta into extra column orders */
+#define WCDL_PH_MERGE 5       /* merging the delta into the full relations */
+#define WCDL_PH_LOAD 6        /* input sorting and index building at run start */
+#define WCDL_PH_OTHER 7
+#define WCDL_N_PHASES 8
+
+typedef struct {
+  uint64_t rounds;           /* semi-naive rounds over all recursive strata,
+                                each stratum's last (empty) round included */
+  uint64_t derived_rows;     /* sum of the final sizes of every relation that
+                                is the head of some rule */
+  uint64_t candidate_rows;   /* rows written by materialize kernels (before
+                                dedup), summed over the run */
+  uint64_t join_units;       /* sum of T (histogram work units) over all joins */
+  double wall_ms;            /* host wall time of the run */
+  double phase_ms[WCDL_N_PHASES];
+  /* Device time of the join kernels, from HIP events recorded around each
+   * launch on the stream that runs it: [0] count (Alg. 1 Phase 2),
+   * [1] materialize (Phase 3, including the cross-product decode path),
+   * [2] histogram (Phase 1). */
+  double kernel_ms[4];
+  uint64_t kernel_launches[4];
+  uint64_t candidates_checked; /* candidate values tested by materialize
+                                  kernels (one per element of the smallest
+                                  list of every intersection) */
+} wcdl_run_stats;
+
+/* Evaluate every stratum to its fixpoint (Sec. 2 stratification; the loop of
+ * Sec. 4 stops when the deduplicated delta is empty).  Derived relations are
+ * recomputed from the loaded facts on every call.  stats may be NULL.  On
+ * WCDL_E_BUDGET or WCDL_E_NOMEM the derived relations keep the last completed
+ * round and the engine stays usable. */
+wcdl_status wcdl_run(wcdl_engine* e, wcdl_run_stats* stats);
+
+/* Rows currently held by a relation (after wcdl_run: its least-model size). */
+wcdl_status wcdl_relation_size(const wcdl_engine* e, uint32_t rel, uint64_t* n_rows);
+
+/* Copy a relation out, sorted and deduplicated.  cols_out[j] receives column
+ * j (capacity uint32 values each); on_device selects device or host
+ * destination pointers.  *n_written receives the number of rows copied
+ * (min(size, capacity)); use wcdl_relation_size first. */
+wcdl_status wcdl_read_columns(const wcdl_engine* e, uint32_t rel, uint32_t* const* cols_out,
+                              uint64_t capacity, uint64_t* n_written, int on_device);
+
+/* Sizes of a relation's per-round deltas in its (recursive) stratum during
+ * the last run: |delta_0|, |delta_1|, ..., ending with the empty one.
+ * Writes min(count, cap) entries; *count receives the total. */
+wcdl_status wcdl_delta_sizes(const wcdl_engine* e, uint32_t rel, uint64_t* out, uint64_t cap,
+                             uint64_t* count);
+
+/* ---- Host-side views of the work partition (Sec. 5, Alg. 2 and the
+ * work-unit decode), exported so the partitioner can be checked without a
+ * GPU; the kernels use the same functions. ------------------------------ */
+
+/* Slice of workgroup b among p over T units: [*b_s, *b_e) with
+ * b_s = b * ceil(T/p), b_e = min(b_s + ceil(T/p), T). */
+void wcdl_work_slice(uint64_t T, uint64_t p, uint64_t b, uint64_t* b_s, uint64_t* b_e);
+
+/* Owner of work unit g under the inclusive prefix sums C[0..K): the first
+ * key k with C[k] > g (so key k owns [C[k-1], C[k]), C[-1] = 0). */
+uint64_t wcdl_owner_key(const uint64_t* C, uint64_t K, uint64_t g);
+
+/* Decode unit g of a two-level cross product into (key, i1, i2):
+ * local = g - C[key-1], i1 = local / d2[key], i2 = local % d2[key]. */
+void wcdl_decode_unit(const uint64_t* C, uint64_t K, const uint32_t* d2, uint64_t g,
+                      uint64_t* key, uint64_t* i1, uint64_t* i2);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WCDL_H */

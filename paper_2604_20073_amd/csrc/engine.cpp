@@ -1,0 +1,1655 @@
+// Host side of the engine: rule parsing and validation, stratification,
+// join planning, the relation store and the semi-naive driver, behind the C
+// ABI declared in wcdl.h.  Every step of evaluation runs in the HIP kernels
+// of prim.hip and wcoj.hip; this file only plans, allocates and launches.
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <functional>
+#include <memory>
+#include <numeric>
+#include <set>
+
+#include "wcdl_internal.h"
+
+namespace wcdl {
+
+// ===========================================================================
+// Device memory cache
+// ===========================================================================
+
+size_t DeviceMemory::size_class(size_t bytes) {
+  if (bytes <= 256) return 256;
+  if (bytes <= (1u << 20)) {  // powers of two up to 1 MiB
+    size_t c = 512;
+    while (c < bytes) c <<= 1;
+    return c;
+  }
+  const size_t q = 1u << 20;  // then whole MiB
+  return (bytes + q - 1) / q * q;
+}
+
+void* DeviceMemory::raw_alloc(size_t bytes) {
+  void* p = nullptr;
+  if (user_.alloc) {
+    p = user_.alloc(user_.ctx, bytes, (void*)stream_);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  return p;
+}
+
+void DeviceMemory::raw_free(void* p, size_t bytes) {
+  if (user_.alloc) {
+    if (user_.free) user_.free(user_.ctx, p, bytes, (void*)stream_);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
+void* DeviceMemory::get(size_t bytes) {
+  const size_t c = size_class(bytes);
+  // Reuse a cached block of this class or one up to 25 % larger.
+  auto it = free_.lower_bound(c);
+  if (it != free_.end() && it->first <= c + c / 4) {
+    void* p = it->second;
+    size_t sz = it->first;
+    free_.erase(it);
+    live_[p] = sz;
+    live_bytes_ += sz;
+    return p;
+  }
+  void* p = raw_alloc(c);
+  if (!p) {
+    // Give the cache back and retry once.
+    WCDL_HIP(hipDeviceSynchronize());
+    sync_point();
+    release_cached();
+    p = raw_alloc(c);
+  }
+  if (!p) throw Error(WCDL_E_NOMEM, "device allocation of " + std::to_string(c) + " bytes failed");
+  live_[p] = c;
+  live_bytes_ += c;
+  return p;
+}
+
+void DeviceMemory::put(void* p) {
+  auto it = live_.find(p);
+  if (it == live_.end()) return;
+  pending_.push_back({p, it->second});
+  live_bytes_ -= it->second;
+  live_.erase(it);
+}
+
+void DeviceMemory::sync_point() {
+  for (auto& b : pending_) free_.insert({b.second, b.first});
+  pending_.clear();
+}
+
+void DeviceMemory::release_cached() {
+  for (auto& b : free_) raw_free(b.second, b.first);
+  free_.clear();
+}
+
+DeviceMemory::~DeviceMemory() {
+  (void)hipDeviceSynchronize();
+  sync_point();
+  release_cached();
+  for (auto& b : live_) raw_free(b.first, b.second);
+  live_.clear();
+}
+
+namespace {
+
+// ===========================================================================
+// Program representation
+// ===========================================================================
+
+struct Term {
+  bool var = false;
+  u32 v = 0;
+};
+
+struct Atom {
+  u32 rel = 0;
+  std::vector<Term> t;
+};
+
+enum { OP_LT = 0, OP_LE = 1, OP_NE = 2 };
+
+struct Cmp {
+  u32 op = OP_LT;  // a op b
+  Term a, b;
+};
+
+struct Rule {
+  Atom head;
+  std::vector<Atom> body;
+  std::vector<Cmp> cmps;
+  u32 nvars = 0;
+  std::vector<u32> var_order;  // optional user order (original variable ids)
+};
+
+struct Relation {
+  std::string name;
+  u32 arity = 0;
+  Cols base;                                   // loaded facts, canonical order
+  Cols full;                                   // current relation, canonical order
+  std::map<std::vector<u32>, Cols> full_ord;   // other column orders of full
+  std::map<std::vector<u32>, Cols> delta_ord;  // current delta, by column order
+  std::vector<u64> delta_sizes;
+  bool derived = false;                        // head of some rule
+};
+
+std::vector<u32> canonical(u32 k) {
+  std::vector<u32> o(k);
+  std::iota(o.begin(), o.end(), 0u);
+  return o;
+}
+
+// ===========================================================================
+// Text syntax parser (independent of the C structures' validation below).
+// ===========================================================================
+
+struct Lexer {
+  const std::string& s;
+  size_t i = 0;
+  explicit Lexer(const std::string& src) : s(src) {}
+  void skip() {
+    for (;;) {
+      while (i < s.size() && isspace((unsigned char)s[i])) ++i;
+      if (i < s.size() && s[i] == '%') {
+        while (i < s.size() && s[i] != '\n') ++i;
+      } else if (i + 1 < s.size() && s[i] == '/' && s[i + 1] == '/') {
+        while (i < s.size() && s[i] != '\n') ++i;
+      } else {
+        return;
+      }
+    }
+  }
+  bool at_end() { skip(); return i >= s.size(); }
+  bool lit(const char* t) {
+    skip();
+    size_t n = strlen(t);
+    if (s.compare(i, n, t) == 0) { i += n; return true; }
+    return false;
+  }
+  bool peek(const char* t) {
+    skip();
+    return s.compare(i, strlen(t), t) == 0;
+  }
+  bool ident(std::string& out) {
+    skip();
+    if (i < s.size() && (isalpha((unsigned char)s[i]) || s[i] == '_')) {
+      size_t j = i + 1;
+      while (j < s.size() && (isalnum((unsigned char)s[j]) || s[j] == '_')) ++j;
+      out = s.substr(i, j - i);
+      i = j;
+      return true;
+    }
+    return false;
+  }
+  int number(u32& out) {  // 1 ok, 0 none, -1 overflow
+    skip();
+    if (i >= s.size() || !isdigit((unsigned char)s[i])) return 0;
+    u64 v = 0;
+    while (i < s.size() && isdigit((unsigned char)s[i])) {
+      v = v * 10 + (u64)(s[i++] - '0');
+      if (v > 0xffffffffull) return -1;
+    }
+    out = (u32)v;
+    return 1;
+  }
+  [[noreturn]] void fail(const std::string& m) {
+    throw Error(WCDL_E_PARSE, m + " at offset " + std::to_string(i));
+  }
+};
+
+// ===========================================================================
+// Engine
+// ===========================================================================
+
+struct Version;
+
+}  // namespace
+}  // namespace wcdl
+
+struct wcdl_engine {
+  wcdl_config cfg{};
+  std::vector<hipStream_t> streams;
+  bool own_streams = false;
+  std::unique_ptr<wcdl::DeviceMemory> mem;
+  std::vector<wcdl::Relation> rels;
+  std::map<std::string, uint32_t> rel_ids;
+  std::vector<wcdl::Rule> rules;
+  std::string err;
+  uint64_t* pinned = nullptr;  // host-pinned scratch for device->host scalars
+  uint32_t helper_count = 0;
+  wcdl_run_stats last{};
+};
+
+namespace wcdl {
+namespace {
+
+using Engine = wcdl_engine;
+
+Ctx ctx(Engine* e, size_t s = 0) { return Ctx{e->mem.get(), e->streams[s % e->streams.size()]}; }
+
+void sync_all(Engine* e) {
+  for (auto s : e->streams) WCDL_HIP(hipStreamSynchronize(s));
+  e->mem->sync_point();
+}
+
+u32 bits_of(u32 orv) {
+  u32 b = 0;
+  while (b < 32 && (orv >> b)) ++b;
+  return b;
+}
+
+// Sorted copy of k columns (pointers in the target order), deduplicated if
+// `dedup`.  Returns a Cols holding `order`.
+Cols sort_rows(Engine* e, size_t si, const std::vector<u32>& order,
+               const std::vector<const u32*>& in, u64 n, bool dedup) {
+  Ctx c = ctx(e, si);
+  const u32 k = (u32)in.size();
+  Cols out;
+  out.order = order;
+  if (n == 0) {
+    for (u32 j = 0; j < k; ++j) out.col.emplace_back();
+    out.n = 0;
+    return out;
+  }
+  DBuf<u32> d_or(c.mem, k);
+  column_or(c, k, in.data(), n, d_or.get());
+  std::vector<u32> h_or(k);
+  WCDL_HIP(hipMemcpyAsync(h_or.data(), d_or.get(), k * sizeof(u32), hipMemcpyDeviceToHost, c.s));
+  WCDL_HIP(hipStreamSynchronize(c.s));
+  std::vector<u32> bits(k);
+  for (u32 j = 0; j < k; ++j) bits[j] = bits_of(h_or[j]);
+  std::vector<DBuf<u32>> sorted;
+  std::vector<u32*> sp;
+  for (u32 j = 0; j < k; ++j) {
+    sorted.emplace_back(c.mem, n);
+    sp.push_back(sorted.back().get());
+  }
+  radix_sort_rows(c, k, in.data(), sp.data(), n, bits.data());
+  if (!dedup) {
+    out.col = std::move(sorted);
+    out.n = n;
+    return out;
+  }
+  std::vector<DBuf<u32>> uq;
+  std::vector<u32*> up;
+  for (u32 j = 0; j < k; ++j) {
+    uq.emplace_back(c.mem, n);
+    up.push_back(uq.back().get());
+  }
+  std::vector<const u32*> sc(sp.begin(), sp.end());
+  out.n = unique_rows(c, k, sc.data(), n, up.data());
+  out.col = std::move(uq);
+  return out;
+}
+
+// A copy of `src` (any order) re-sorted into `order` (a permutation of the
+// logical columns).
+Cols reorder(Engine* e, size_t si, const Cols& src, const std::vector<u32>& order) {
+  std::vector<const u32*> in;
+  for (u32 j = 0; j < order.size(); ++j) {
+    u32 logical = order[j];
+    u32 pos = (u32)(std::find(src.order.begin(), src.order.end(), logical) - src.order.begin());
+    in.push_back(src.col[pos].get());
+  }
+  return sort_rows(e, si, order, in, src.n, false);
+}
+
+Cols copy_cols(Engine* e, const Cols& src) {
+  Cols out;
+  out.order = src.order;
+  out.n = src.n;
+  for (auto& c : src.col) {
+    out.col.emplace_back(e->mem.get(), src.n);
+    if (src.n) copy_u32(ctx(e), out.col.back().get(), c.get(), src.n);
+  }
+  return out;
+}
+
+Cols empty_cols(u32 k, const std::vector<u32>& order) {
+  Cols c;
+  c.order = order;
+  for (u32 j = 0; j < k; ++j) c.col.emplace_back();
+  (void)k;
+  return c;
+}
+
+// rows(a) \ rows(b), both sorted unique in the same order.
+Cols difference(Engine* e, size_t si, const Cols& a, const Cols& b) {
+  Cols out;
+  out.order = a.order;
+  const u32 k = a.arity();
+  if (a.n == 0) {
+    for (u32 j = 0; j < k; ++j) out.col.emplace_back();
+    return out;
+  }
+  std::vector<u32*> op;
+  for (u32 j = 0; j < k; ++j) {
+    out.col.emplace_back(e->mem.get(), a.n);
+    op.push_back(out.col.back().get());
+  }
+  auto ap = a.ptrs(), bp = b.ptrs();
+  out.n = set_difference(ctx(e, si), k, ap.data(), a.n, bp.data(), b.n, op.data());
+  return out;
+}
+
+// a U b for disjoint sorted-unique runs in the same order.
+Cols merged(Engine* e, size_t si, const Cols& a, const Cols& b) {
+  Cols out;
+  out.order = a.order;
+  const u32 k = a.arity();
+  out.n = a.n + b.n;
+  std::vector<u32*> op;
+  for (u32 j = 0; j < k; ++j) {
+    out.col.emplace_back(e->mem.get(), out.n);
+    op.push_back(out.col.back().get());
+  }
+  if (out.n) {
+    auto ap = a.ptrs(), bp = b.ptrs();
+    merge_disjoint(ctx(e, si), k, ap.data(), a.n, bp.data(), b.n, op.data());
+  }
+  return out;
+}
+
+// ===========================================================================
+// Planning
+// ===========================================================================
+
+// One body atom as a version reads it.
+struct AtomUse {
+  u32 rel = 0;
+  bool delta = false;
+  std::vector<u32> order;     // index order: logical column per position
+  std::vector<int> pos_var;   // per position: variable id or -1 (constant)
+  std::vector<u32> pos_const;
+  u32 nconst = 0;
+};
+
+struct Version {
+  u32 rule = 0;
+  int delta_atom = -1;
+  u32 head_rel = 0;
+  bool dead = false;            // a comparison between constants fails
+  std::vector<u32> level_var;   // variable id at each level
+  std::vector<AtomUse> atoms;
+  std::vector<std::vector<u32>> src_pos;  // per level, per source: column position in its atom
+  DPlan plan{};                 // pointers filled at evaluation time
+  bool sorted_output = false;   // rows come out sorted by head columns, unique
+  u32 lds_bytes = 0;
+};
+
+// A rule with repeated variables inside one atom rewritten: each repeat
+// becomes a fresh variable constrained equal (<= both ways) to the first.
+Rule normalize(const Rule& r0) {
+  Rule r = r0;
+  for (auto& a : r.body) {
+    std::set<u32> seen;
+    for (auto& t : a.t) {
+      if (!t.var) continue;
+      if (seen.count(t.v)) {
+        u32 fresh = r.nvars++;
+        Cmp c1, c2;
+        c1.op = OP_LE; c1.a = {true, fresh}; c1.b = {true, t.v};
+        c2.op = OP_LE; c2.a = {true, t.v}; c2.b = {true, fresh};
+        r.cmps.push_back(c1);
+        r.cmps.push_back(c2);
+        t.v = fresh;
+      } else {
+        seen.insert(t.v);
+      }
+    }
+  }
+  return r;
+}
+
+std::vector<u32> choose_order(const Rule& r, int delta_atom) {
+  // Body variables in order of first appearance.
+  std::vector<u32> vars;
+  std::vector<int> first(r.nvars, -1);
+  for (auto& a : r.body)
+    for (auto& t : a.t)
+      if (t.var && first[t.v] < 0) {
+        first[t.v] = (int)vars.size();
+        vars.push_back(t.v);
+      }
+  if (!r.var_order.empty() && r.var_order.size() == vars.size()) {
+    // A user order over the original variables; fresh variables (from
+    // repeats) are not in it, so it is only used when the sizes agree.
+    return r.var_order;
+  }
+  std::vector<u32> occ(r.nvars, 0);
+  for (auto& a : r.body) {
+    std::set<u32> in;
+    for (auto& t : a.t)
+      if (t.var) in.insert(t.v);
+    for (u32 v : in) occ[v]++;
+  }
+  std::vector<int> head_pos(r.nvars, 1 << 20);
+  for (size_t h = 0; h < r.head.t.size(); ++h)
+    if (r.head.t[h].var && head_pos[r.head.t[h].v] == (1 << 20)) head_pos[r.head.t[h].v] = (int)h;
+
+  std::vector<bool> bound(r.nvars, false);
+  std::vector<u32> order;
+  auto connected_count = [&](u32 v) {
+    u32 c = 0;
+    for (auto& a : r.body) {
+      bool has_v = false, has_b = false;
+      for (auto& t : a.t)
+        if (t.var) {
+          if (t.v == v) has_v = true;
+          else if (bound[t.v]) has_b = true;
+        }
+      if (has_v && has_b) ++c;
+    }
+    return c;
+  };
+  // Without a delta atom, try the head's own variable order: if it covers
+  // every body variable once and stays connected, the output comes out
+  // sorted and unique.
+  if (delta_atom < 0) {
+    std::vector<u32> hv;
+    std::set<u32> hs;
+    bool ok = true;
+    for (auto& t : r.head.t) {
+      if (!t.var) continue;
+      if (hs.count(t.v)) { ok = false; break; }
+      hs.insert(t.v);
+      hv.push_back(t.v);
+    }
+    if (ok && hv.size() == vars.size()) {
+      for (size_t i = 0; i < hv.size() && ok; ++i) {
+        if (i > 0 && connected_count(hv[i]) == 0) ok = false;
+        bound[hv[i]] = true;
+      }
+      if (ok) return hv;
+      std::fill(bound.begin(), bound.end(), false);
+    }
+  }
+  // Root: a variable of the delta atom (delta-first), most shared first.
+  auto better = [&](u32 a, u32 b, bool use_conn) {  // is a preferred over b
+    if (use_conn) {
+      u32 ca = connected_count(a), cb = connected_count(b);
+      if (ca != cb) return ca > cb;
+    }
+    if (occ[a] != occ[b]) return occ[a] > occ[b];
+    if (head_pos[a] != head_pos[b]) return head_pos[a] < head_pos[b];
+    return first[a] < first[b];
+  };
+  std::vector<u32> cand;
+  if (delta_atom >= 0) {
+    for (auto& t : r.body[delta_atom].t)
+      if (t.var && std::find(cand.begin(), cand.end(), t.v) == cand.end()) cand.push_back(t.v);
+  } else {
+    cand = vars;
+  }
+  u32 root = cand[0];
+  for (u32 v : cand)
+    if (better(v, root, false)) root = v;
+  order.push_back(root);
+  bound[root] = true;
+  while (order.size() < vars.size()) {
+    int best = -1;
+    bool any_conn = false;
+    for (u32 v : vars)
+      if (!bound[v] && connected_count(v) > 0) any_conn = true;
+    for (u32 v : vars) {
+      if (bound[v]) continue;
+      if (any_conn && connected_count(v) == 0) continue;
+      if (best < 0 || better(v, (u32)best, true)) best = (int)v;
+    }
+    order.push_back((u32)best);
+    bound[best] = true;
+  }
+  return order;
+}
+
+constexpr u32 LDS_BUDGET = 60 * 1024;
+
+// Build a version of rule `ri` with atom `delta_atom` read from the delta (or
+// -1 for none).  Pointers are filled later.
+Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
+  const Rule r = normalize(e->rules[ri]);
+  Version v;
+  v.rule = ri;
+  v.delta_atom = delta_atom;
+  v.head_rel = r.head.rel;
+  v.level_var = choose_order(r, delta_atom);
+  const u32 m = (u32)v.level_var.size();
+  if (m == 0) throw Error(WCDL_E_UNSUPPORTED, "rule without body variables");
+  if (m > (u32)MAXV) throw Error(WCDL_E_UNSUPPORTED, "rule has more than 8 variables");
+  if (r.body.size() > (size_t)MAXN) throw Error(WCDL_E_UNSUPPORTED, "rule has more than 8 body atoms");
+  std::vector<int> level_of(r.nvars, -1);
+  for (u32 L = 0; L < m; ++L) level_of[v.level_var[L]] = (int)L;
+
+  DPlan& P = v.plan;
+  memset(&P, 0, sizeof(P));
+  P.m = m;
+  P.natoms = (u32)r.body.size();
+  // Atom index orders: constants first, then variables by level.
+  for (size_t ai = 0; ai < r.body.size(); ++ai) {
+    const Atom& a = r.body[ai];
+    AtomUse u;
+    u.rel = a.rel;
+    u.delta = ((int)ai == delta_atom);
+    std::vector<u32> cols(a.t.size());
+    std::iota(cols.begin(), cols.end(), 0u);
+    std::stable_sort(cols.begin(), cols.end(), [&](u32 x, u32 y) {
+      int kx = a.t[x].var ? level_of[a.t[x].v] : -1;
+      int ky = a.t[y].var ? level_of[a.t[y].v] : -1;
+      return kx < ky;
+    });
+    for (u32 c : cols) {
+      u.order.push_back(c);
+      if (a.t[c].var) {
+        u.pos_var.push_back((int)a.t[c].v);
+        u.pos_const.push_back(0);
+      } else {
+        u.pos_var.push_back(-1);
+        u.pos_const.push_back(a.t[c].v);
+        u.nconst++;
+      }
+    }
+    P.atom_nconst[ai] = u.nconst;
+    for (u32 c = 0; c < u.nconst; ++c) P.atom_const[ai][c] = u.pos_const[c];
+    v.atoms.push_back(u);
+  }
+  // Levels: sources, bounds, filters.
+  v.src_pos.assign(m, {});
+  for (u32 L = 0; L < m; ++L) {
+    DLevel& lv = P.lvl[L];
+    for (u32 a = 0; a < (u32)MAXN; ++a) lv.atom_src[a] = NONE;
+    for (size_t ai = 0; ai < v.atoms.size(); ++ai) {
+      const AtomUse& u = v.atoms[ai];
+      for (size_t p = 0; p < u.pos_var.size(); ++p) {
+        if (u.pos_var[p] == (int)v.level_var[L]) {
+          DSource& s = lv.src[lv.nsrc];
+          s.atom = (u32)ai;
+          s.last = (p + 1 == u.pos_var.size()) ? 1u : 0u;
+          v.src_pos[L].push_back((u32)p);
+          lv.atom_src[ai] = lv.nsrc;
+          lv.nsrc++;
+        }
+      }
+    }
+  }
+  auto operand = [&](const Term& t) {
+    DOperand o;
+    o.is_var = t.var ? 1u : 0u;
+    o.v = t.var ? (u32)level_of[t.v] : t.v;
+    return o;
+  };
+  for (const Cmp& c : r.cmps) {
+    int la = c.a.var ? level_of[c.a.v] : -1;
+    int lb = c.b.var ? level_of[c.b.v] : -1;
+    if (la < 0 && lb < 0) {
+      bool ok = c.op == OP_LT ? c.a.v < c.b.v : c.op == OP_LE ? c.a.v <= c.b.v : c.a.v != c.b.v;
+      if (!ok) v.dead = true;
+      continue;
+    }
+    if (c.a.var && c.b.var && c.a.v == c.b.v) {
+      if (c.op != OP_LE) v.dead = true;
+      continue;
+    }
+    const int L = std::max(la, lb);
+    DLevel& lv = P.lvl[L];
+    const bool a_is_level = (la == L);
+    const Term& other = a_is_level ? c.b : c.a;
+    if (c.op == OP_NE) {
+      if (lv.nne >= (u32)MAXF) throw Error(WCDL_E_UNSUPPORTED, "too many != filters on one variable");
+      lv.ne[lv.nne++] = operand(other);
+      continue;
+    }
+    if (lv.nbnd >= (u32)MAXB) throw Error(WCDL_E_UNSUPPORTED, "too many bounds on one variable");
+    DBound& b = lv.bnd[lv.nbnd++];
+    b.o = operand(other);
+    b.adj = (c.op == OP_LT) ? 1u : 0u;
+    b.is_hi = a_is_level ? 1u : 0u;  // x_L < other -> upper bound; other < x_L -> lower
+  }
+  // Root: the delta atom's source at level 0 if it has one there, else the
+  // first level-0 source.
+  {
+    const DLevel& l0 = P.lvl[0];
+    P.root_src = 0;
+    if (delta_atom >= 0 && l0.atom_src[delta_atom] != NONE) P.root_src = l0.atom_src[delta_atom];
+  }
+  // Head.
+  P.head_arity = (u32)r.head.t.size();
+  bool sorted = (P.head_arity == m);
+  for (u32 h = 0; h < P.head_arity; ++h) {
+    P.head[h] = operand(r.head.t[h]);
+    if (!(P.head[h].is_var && P.head[h].v == h)) sorted = false;
+  }
+  v.sorted_output = sorted;
+  // Fast paths.
+  if (m >= 2) {
+    const DLevel& leaf = P.lvl[m - 1];
+    P.leaf_fast = (leaf.nsrc == 1 && leaf.src[0].last && leaf.nne == 0) ? 1u : 0u;
+    bool xp = !(flags & WCDL_F_XPROD_OFF);
+    for (u32 L = 1; L < m && xp; ++L) {
+      const DLevel& lv = P.lvl[L];
+      if (lv.nsrc != 1 || lv.nbnd || lv.nne || !lv.src[0].last) { xp = false; break; }
+      // The atom may only hold x_0 and x_L.
+      for (int pv : v.atoms[lv.src[0].atom].pos_var)
+        if (pv >= 0 && level_of[pv] != 0 && level_of[pv] != (int)L) xp = false;
+    }
+    P.xprod = xp ? 1u : 0u;
+  }
+  // LDS layout of the level buffers 0..m-2.
+  auto layout = [&](u32 cap) {
+    u32 w = 0;
+    for (u32 b = 0; b + 1 < m; ++b) {
+      P.off_val[b] = w; w += (b + 1) * cap;
+      P.off_lo[b] = w; w += P.natoms * cap;
+      P.off_hi[b] = w; w += P.natoms * cap;
+      P.off_drv[b] = w; w += cap;
+      P.off_clo[b] = w; w += cap;
+      P.off_chi[b] = w; w += cap;
+      w = (w + 1) & ~1u;
+      P.off_pre[b] = w; w += 2 * cap;
+    }
+    return w;
+  };
+  u32 cap = 512;
+  u32 words = layout(cap);
+  if (words * 4 > LDS_BUDGET) {
+    cap = 256;
+    words = layout(cap);
+  }
+  if (words * 4 > 150 * 1024) throw Error(WCDL_E_UNSUPPORTED, "join too deep for LDS; split the rule");
+  P.cap = cap;
+  P.lds_words = words;
+  v.lds_bytes = words * 4;
+  return v;
+}
+
+// ===========================================================================
+// Stratification (Tarjan, dependencies first)
+// ===========================================================================
+
+std::vector<std::vector<u32>> strata(Engine* e) {
+  const u32 n = (u32)e->rels.size();
+  std::vector<std::vector<u32>> dep(n);
+  for (auto& r : e->rules)
+    for (auto& a : r.body) dep[r.head.rel].push_back(a.rel);
+  std::vector<int> idx(n, -1), low(n, 0);
+  std::vector<bool> on(n, false);
+  std::vector<u32> st;
+  std::vector<std::vector<u32>> out;
+  int counter = 0;
+  std::function<void(u32)> go = [&](u32 v) {
+    idx[v] = low[v] = counter++;
+    st.push_back(v);
+    on[v] = true;
+    for (u32 w : dep[v]) {
+      if (idx[w] < 0) {
+        go(w);
+        low[v] = std::min(low[v], low[w]);
+      } else if (on[w]) {
+        low[v] = std::min(low[v], idx[w]);
+      }
+    }
+    if (low[v] == idx[v]) {
+      std::vector<u32> comp;
+      for (;;) {
+        u32 w = st.back();
+        st.pop_back();
+        on[w] = false;
+        comp.push_back(w);
+        if (w == v) break;
+      }
+      std::sort(comp.begin(), comp.end());
+      out.push_back(comp);
+    }
+  };
+  for (u32 v = 0; v < n; ++v)
+    if (idx[v] < 0) go(v);
+  return out;
+}
+
+// ===========================================================================
+// Evaluation of a batch of rule versions (phase-aligned across streams)
+// ===========================================================================
+
+struct Stats {
+  double phase[WCDL_N_PHASES] = {0};
+  u64 candidates = 0;
+  u64 units = 0;
+  double kernel_ms[4] = {0};
+  u64 launches[4] = {0};
+  u64 examined = 0;
+};
+
+// HIP events around one kernel launch on its stream; read after a sync.
+struct KernelTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  int kind = -1;
+  void start(hipStream_t s, int k) {
+    kind = k;
+    WCDL_HIP(hipEventCreate(&a));
+    WCDL_HIP(hipEventCreate(&b));
+    WCDL_HIP(hipEventRecord(a, s));
+  }
+  void stop(hipStream_t s) { WCDL_HIP(hipEventRecord(b, s)); }
+  void collect(Stats& st) {
+    if (kind < 0) return;
+    float ms = 0;
+    WCDL_HIP(hipEventElapsedTime(&ms, a, b));
+    st.kernel_ms[kind] += ms;
+    st.launches[kind] += 1;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    kind = -1;
+  }
+  ~KernelTimer() {
+    if (kind >= 0) {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  }
+};
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t).count();
+}
+
+// The sorted copy of (relation, delta?, order) a version reads; built on
+// demand from the canonical copy.
+const Cols& get_cols(Engine* e, u32 rel, bool delta, const std::vector<u32>& order) {
+  Relation& R = e->rels[rel];
+  const std::vector<u32> canon = canonical(R.arity);
+  if (!delta) {
+    if (order == canon) return R.full;
+    auto it = R.full_ord.find(order);
+    if (it == R.full_ord.end()) it = R.full_ord.emplace(order, reorder(e, 0, R.full, order)).first;
+    return it->second;
+  }
+  auto it = R.delta_ord.find(order);
+  if (it == R.delta_ord.end()) {
+    auto ct = R.delta_ord.find(canon);
+    if (ct == R.delta_ord.end()) throw Error(WCDL_E_STATE, "delta not available");
+    it = R.delta_ord.emplace(order, reorder(e, 0, ct->second, order)).first;
+  }
+  return it->second;
+}
+
+// Per-version evaluation state across the phases of one batch.
+struct VRun {
+  Version* v = nullptr;
+  size_t si = 0;
+  bool skip = false;
+  DPlan* host_plan = nullptr;  // pinned staging copy
+  DBuf<DPlan> d_plan;
+  DBuf<u32> rng0;
+  DBuf<u32> flags;
+  DBuf<u64> pos;
+  DBuf<u32> U, S;
+  DBuf<u64> W, C;
+  DBuf<u32> klo, kd;
+  DBuf<u64> counts, offsets;
+  DBuf<u64> scal;  // [0] K, [1] T, [2] total, [3] materialize error flag
+  u64 K = 0, T = 0, total = 0;
+  u64 out_off = 0;
+  RootSpace rs{};
+  Partition part{};
+  u32 root_atom = 0, root_pos = 0;
+  KernelTimer t_hist, t_count, t_mat;
+};
+
+constexpr u64 NCU = 256;
+
+// Evaluate a set of rule versions over the current relations; returns the
+// raw head rows per head relation (canonical column order, unsorted).
+std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
+  const bool seq = (e->cfg.flags & WCDL_F_STREAMS_OFF) != 0;
+  const u32 flags = e->cfg.flags;
+  std::vector<VRun> runs(vs.size());
+  static_assert(sizeof(DPlan) < 16384, "plan size");
+  // Pinned staging for plans (one slot per version) and scalars.
+  std::vector<DPlan*> staging;
+  for (size_t i = 0; i < vs.size(); ++i) {
+    void* h = nullptr;
+    WCDL_HIP(hipHostMalloc(&h, sizeof(DPlan), hipHostMallocDefault));
+    staging.push_back(static_cast<DPlan*>(h));
+  }
+  struct Staging {
+    std::vector<DPlan*>& v;
+    ~Staging() { for (auto* p : v) (void)hipHostFree(p); }
+  } guard{staging};
+
+  auto t_hist = Clock::now();
+  // ---- Inputs: every version's sorted copies.  Missing column orders are
+  // built on stream 0; fence it before any other stream reads them.
+  for (size_t i = 0; i < vs.size(); ++i) {
+    VRun& R = runs[i];
+    Version& v = vs[i];
+    R.v = &v;
+    R.si = seq ? 0 : i % e->streams.size();
+    R.host_plan = staging[i];
+    if (v.dead) { R.skip = true; continue; }
+    DPlan& P = v.plan;
+    for (size_t ai = 0; ai < v.atoms.size(); ++ai) {
+      const AtomUse& u = v.atoms[ai];
+      const Cols& cc = get_cols(e, u.rel, u.delta, u.order);
+      if (cc.n == 0) R.skip = true;
+      if (cc.n >= 0xffffffffull) throw Error(WCDL_E_UNSUPPORTED, "join source exceeds 2^32-1 rows");
+      P.atom_n[ai] = (u32)cc.n;
+      for (size_t p = 0; p < u.order.size(); ++p) P.atom_col[ai][p] = cc.col[p].get();
+    }
+  }
+  WCDL_HIP(hipStreamSynchronize(e->streams[0]));
+  // ---- Phase A: plan upload, constant narrowing, root-key flags.
+  for (size_t i = 0; i < vs.size(); ++i) {
+    VRun& R = runs[i];
+    Version& v = vs[i];
+    if (R.skip) continue;
+    DPlan& P = v.plan;
+    for (u32 L = 0; L < P.m; ++L)
+      for (u32 s = 0; s < P.lvl[L].nsrc; ++s)
+        P.lvl[L].src[s].col = P.atom_col[P.lvl[L].src[s].atom][v.src_pos[L][s]];
+    R.root_atom = P.lvl[0].src[P.root_src].atom;
+    R.root_pos = v.src_pos[0][P.root_src];
+    Ctx c = ctx(e, R.si);
+    *R.host_plan = P;
+    R.d_plan = DBuf<DPlan>(c.mem, 1);
+    WCDL_HIP(hipMemcpyAsync(R.d_plan.get(), R.host_plan, sizeof(DPlan), hipMemcpyHostToDevice, c.s));
+    R.rng0 = DBuf<u32>(c.mem, 2 * MAXN);
+    R.scal = DBuf<u64>(c.mem, 4);
+    fill_u64(c, R.scal.get(), 4, 0);
+    join_init_ranges(c, R.d_plan.get(), P.natoms, R.rng0.get());
+    const u32 n = P.atom_n[R.root_atom];
+    R.flags = DBuf<u32>(c.mem, n);
+    R.pos = DBuf<u64>(c.mem, n);
+    join_root_flags(c, P.atom_col[R.root_atom][R.root_pos], R.rng0.get(), R.root_atom, n,
+                    R.flags.get(), R.pos.get(), R.scal.get());
+  }
+  sync_all(e);
+  // ---- Phase B: root keys, histogram, prefix sums.
+  for (auto& R : runs) {
+    if (R.skip) continue;
+    Ctx c = ctx(e, R.si);
+    WCDL_HIP(hipMemcpy(&R.K, R.scal.get(), sizeof(u64), hipMemcpyDeviceToHost));
+    if (R.K == 0) { R.skip = true; continue; }
+    const DPlan& P = R.v->plan;
+    const u32 n = P.atom_n[R.root_atom];
+    R.U = DBuf<u32>(c.mem, R.K);
+    R.S = DBuf<u32>(c.mem, R.K + 1);
+    join_root_compact(c, P.atom_col[R.root_atom][R.root_pos], R.rng0.get(), R.root_atom, n,
+                      R.flags.get(), R.pos.get(), R.K, R.U.get(), R.S.get());
+    R.W = DBuf<u64>(c.mem, R.K);
+    R.C = DBuf<u64>(c.mem, R.K);
+    if (P.xprod) {
+      R.klo = DBuf<u32>(c.mem, (u64)P.m * R.K);
+      R.kd = DBuf<u32>(c.mem, (u64)P.m * R.K);
+    }
+    R.rs = RootSpace{R.U.get(), R.S.get(), R.C.get(), R.K, 0, R.rng0.get()};
+    R.t_hist.start(c.s, 2);
+    join_histogram(c, R.d_plan.get(), R.rs, R.W.get(), P.xprod ? R.klo.get() : nullptr,
+                   P.xprod ? R.kd.get() : nullptr, P.m);
+    R.t_hist.stop(c.s);
+    scan_u64_incl(c, R.W.get(), R.C.get(), R.K, R.scal.get() + 1);
+  }
+  sync_all(e);
+  st.phase[WCDL_PH_HISTOGRAM] += ms_since(t_hist);
+  // ---- Phase C: count pass (Alg. 1 Phase 2) and offsets.
+  auto t_count = Clock::now();
+  for (auto& R : runs) {
+    if (R.skip) continue;
+    WCDL_HIP(hipMemcpy(&R.T, R.scal.get() + 1, sizeof(u64), hipMemcpyDeviceToHost));
+    if (R.T == 0) { R.skip = true; continue; }
+    R.rs.T = R.T;
+    st.units += R.T;
+    const DPlan& P = R.v->plan;
+    if (P.xprod) {
+      R.total = R.T;
+      continue;
+    }
+    Ctx c = ctx(e, R.si);
+    u64 p;
+    if (flags & WCDL_F_BALANCE_OFF) {
+      p = R.K;  // one root key per workgroup (the unbalanced baseline)
+      R.part = Partition{p, 0, 1, 0};
+    } else {
+      const u64 wpc = e->cfg.wg_per_cu ? e->cfg.wg_per_cu : 8;
+      p = std::min<u64>(ceil_div(R.T, 64), NCU * wpc);
+      if (p == 0) p = 1;
+      const u64 slice = ceil_div(R.T, p);
+      p = ceil_div(R.T, slice);
+      R.part = Partition{p, slice, 0, 0};
+    }
+    R.counts = DBuf<u64>(c.mem, p);
+    R.offsets = DBuf<u64>(c.mem, p);
+    R.t_count.start(c.s, 0);
+    join_run(c, R.d_plan.get(), R.rs, R.part, R.v->lds_bytes, 0, R.counts.get(), nullptr, 0, p);
+    R.t_count.stop(c.s);
+    scan_u64_excl(c, R.counts.get(), R.offsets.get(), p, R.scal.get() + 2);
+  }
+  sync_all(e);
+  for (auto& R : runs) {
+    if (R.skip || R.v->plan.xprod) continue;
+    WCDL_HIP(hipMemcpy(&R.total, R.scal.get() + 2, sizeof(u64), hipMemcpyDeviceToHost));
+    if (R.total == 0) R.skip = true;
+  }
+  st.phase[WCDL_PH_COUNT] += ms_since(t_count);
+  // ---- Resize: one candidate buffer per head relation.
+  std::map<u32, Cols> out;
+  std::map<u32, u64> rows;
+  for (auto& R : runs) {
+    if (R.skip) continue;
+    R.out_off = rows[R.v->head_rel];
+    rows[R.v->head_rel] += R.total;
+  }
+  u64 need = 0;
+  for (auto& kv : rows) need += kv.second * e->rels[kv.first].arity * 4ull;
+  if (e->cfg.mem_budget_bytes && need * 3 + e->mem->live_bytes() > e->cfg.mem_budget_bytes)
+    throw Error(WCDL_E_BUDGET, "count pass needs " + std::to_string(need) +
+                                   " bytes of candidates, beyond the memory budget");
+  for (auto& kv : rows) {
+    const u32 k = e->rels[kv.first].arity;
+    Cols c;
+    c.order = canonical(k);
+    c.n = kv.second;
+    for (u32 j = 0; j < k; ++j) c.col.emplace_back(e->mem.get(), kv.second);
+    out.emplace(kv.first, std::move(c));
+  }
+  // ---- Phase D: materialize (Alg. 1 Phase 3).
+  auto t_mat = Clock::now();
+  for (auto& R : runs) {
+    if (R.skip) continue;
+    Ctx c = ctx(e, R.si);
+    DPlan& P = R.v->plan;
+    Cols& dst = out.at(R.v->head_rel);
+    for (u32 h = 0; h < P.head_arity; ++h) P.out[h] = dst.col[h].get() + R.out_off;
+    P.out_rows = R.total;
+    P.err = reinterpret_cast<u32*>(R.scal.get() + 3);
+    P.cand = R.scal.get() + 2;  // reused: the total was read already
+    fill_u64(c, R.scal.get() + 2, 1, 0);
+    *R.host_plan = P;
+    WCDL_HIP(hipMemcpyAsync(R.d_plan.get(), R.host_plan, sizeof(DPlan), hipMemcpyHostToDevice, c.s));
+    R.t_mat.start(c.s, 1);
+    if (P.xprod)
+      join_xprod(c, R.d_plan.get(), R.rs, R.klo.get(), R.kd.get(), P.m);
+    else
+      join_run(c, R.d_plan.get(), R.rs, R.part, R.v->lds_bytes, 1, nullptr, R.offsets.get(), 0,
+               R.part.p);
+    R.t_mat.stop(c.s);
+    st.candidates += R.total;
+  }
+  sync_all(e);
+  for (auto& R : runs) {
+    if (R.skip) continue;
+    u64 flag = 0, examined = 0;
+    WCDL_HIP(hipMemcpy(&flag, R.scal.get() + 3, sizeof(u64), hipMemcpyDeviceToHost));
+    if (flag) throw Error(WCDL_E_DEVICE, "internal error: materialize produced more rows than counted");
+    WCDL_HIP(hipMemcpy(&examined, R.scal.get() + 2, sizeof(u64), hipMemcpyDeviceToHost));
+    st.examined += R.v->plan.xprod ? R.total : examined;
+  }
+  for (auto& R : runs) {
+    R.t_hist.collect(st);
+    R.t_count.collect(st);
+    R.t_mat.collect(st);
+  }
+  st.phase[WCDL_PH_MATERIALIZE] += ms_since(t_mat);
+  return out;
+}
+
+// Compute new rows = unique(cand) \ full, merge them into full (and into
+// every other maintained column order of full).  Returns the new rows.
+Cols absorb(Engine* e, u32 rel, Cols&& cand, bool presorted, Stats& st) {
+  Relation& R = e->rels[rel];
+  auto t = Clock::now();
+  Cols d;
+  if (presorted && R.full.n == 0) {
+    d = std::move(cand);
+  } else {
+    Cols s = sort_rows(e, 0, cand.order, std::vector<const u32*>(cand.ptrs()), cand.n, true);
+    cand = Cols();
+    d = difference(e, 0, s, R.full);
+  }
+  WCDL_HIP(hipStreamSynchronize(e->streams[0]));
+  st.phase[WCDL_PH_DELTA] += ms_since(t);
+  t = Clock::now();
+  if (d.n) {
+    if (R.full.n == 0) {
+      R.full = copy_cols(e, d);
+    } else {
+      R.full = merged(e, 0, R.full, d);
+    }
+    for (auto& kv : R.full_ord) {
+      Cols ds = reorder(e, 0, d, kv.first);
+      kv.second = merged(e, 0, kv.second, ds);
+    }
+  }
+  WCDL_HIP(hipStreamSynchronize(e->streams[0]));
+  st.phase[WCDL_PH_MERGE] += ms_since(t);
+  return d;
+}
+
+void run_program(Engine* e, wcdl_run_stats* stats_out) {
+  auto t0 = Clock::now();
+  Stats st;
+  for (auto& R : e->rels) {
+    R.full = copy_cols(e, R.base);
+    R.full_ord.clear();
+    R.delta_ord.clear();
+    R.delta_sizes.clear();
+    R.derived = false;
+  }
+  for (auto& r : e->rules) e->rels[r.head.rel].derived = true;
+  sync_all(e);
+  u64 rounds = 0;
+  for (const auto& comp : strata(e)) {
+    std::set<u32> in(comp.begin(), comp.end());
+    std::vector<u32> exit_rules, rec_rules;
+    for (u32 ri = 0; ri < e->rules.size(); ++ri) {
+      const Rule& r = e->rules[ri];
+      if (!in.count(r.head.rel)) continue;
+      bool rec = false;
+      for (auto& a : r.body)
+        if (in.count(a.rel)) rec = true;
+      (rec ? rec_rules : exit_rules).push_back(ri);
+    }
+    if (exit_rules.empty() && rec_rules.empty()) continue;
+    // Exit rules read finished relations only.
+    if (!exit_rules.empty()) {
+      std::vector<Version> vs;
+      for (u32 ri : exit_rules) vs.push_back(plan_version(e, ri, -1, e->cfg.flags));
+      auto cand = eval_batch(e, vs, st);
+      for (auto& kv : cand) {
+        u32 nv = 0;
+        bool sorted = true;
+        for (auto& v : vs)
+          if (v.head_rel == kv.first) { ++nv; sorted = sorted && v.sorted_output; }
+        absorb(e, kv.first, std::move(kv.second), rec_rules.empty() && nv == 1 && sorted, st);
+      }
+    }
+    if (rec_rules.empty()) continue;
+    // Semi-naive rounds: delta_0 is everything the stratum holds so far.
+    for (u32 rel : comp) {
+      Relation& R = e->rels[rel];
+      R.delta_ord.clear();
+      R.delta_ord.emplace(canonical(R.arity), copy_cols(e, R.full));
+      R.delta_sizes.push_back(R.full.n);
+    }
+    sync_all(e);  // the copies are read from every stream
+    std::vector<Version> vs;
+    for (u32 ri : rec_rules) {
+      const Rule& r = e->rules[ri];
+      for (u32 j = 0; j < r.body.size(); ++j)
+        if (in.count(r.body[j].rel)) vs.push_back(plan_version(e, ri, (int)j, e->cfg.flags));
+    }
+    for (;;) {
+      auto cand = eval_batch(e, vs, st);
+      std::map<u32, Cols> nd;
+      bool any = false;
+      for (u32 rel : comp) {
+        auto it = cand.find(rel);
+        Cols d;
+        if (it != cand.end()) {
+          d = absorb(e, rel, std::move(it->second), false, st);
+        } else {
+          d = empty_cols(e->rels[rel].arity, canonical(e->rels[rel].arity));
+        }
+        if (d.n) any = true;
+        nd.emplace(rel, std::move(d));
+      }
+      for (u32 rel : comp) {
+        Relation& R = e->rels[rel];
+        R.delta_sizes.push_back(nd[rel].n);
+        R.delta_ord.clear();
+        R.delta_ord.emplace(canonical(R.arity), std::move(nd[rel]));
+      }
+      ++rounds;
+      sync_all(e);
+      if (!any) break;
+    }
+    for (u32 rel : comp) e->rels[rel].delta_ord.clear();
+  }
+  sync_all(e);
+  wcdl_run_stats s{};
+  s.rounds = rounds;
+  for (auto& R : e->rels)
+    if (R.derived) s.derived_rows += R.full.n;
+  s.candidate_rows = st.candidates;
+  s.join_units = st.units;
+  s.wall_ms = ms_since(t0);
+  for (int i = 0; i < WCDL_N_PHASES; ++i) s.phase_ms[i] = st.phase[i];
+  for (int i = 0; i < 4; ++i) {
+    s.kernel_ms[i] = st.kernel_ms[i];
+    s.kernel_launches[i] = st.launches[i];
+  }
+  s.candidates_checked = st.examined;
+  e->last = s;
+  if (stats_out) *stats_out = s;
+}
+
+// ===========================================================================
+// Rule construction and validation
+// ===========================================================================
+
+void validate_rule(Engine* e, const Rule& r) {
+  auto check_atom = [&](const Atom& a) {
+    if (a.rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
+    if (a.t.size() != e->rels[a.rel].arity)
+      throw Error(WCDL_E_ARITY, "atom of " + e->rels[a.rel].name + " has the wrong arity");
+    for (auto& t : a.t)
+      if (t.var && t.v >= r.nvars) throw Error(WCDL_E_INVALID, "variable id out of range");
+  };
+  check_atom(r.head);
+  if (r.body.empty()) throw Error(WCDL_E_UNSAFE_RULE, "a rule needs at least one body atom");
+  if (r.body.size() > (size_t)MAXN) throw Error(WCDL_E_UNSUPPORTED, "more than 8 body atoms");
+  if (r.cmps.size() > (size_t)WCDL_MAX_CMPS) throw Error(WCDL_E_UNSUPPORTED, "more than 8 comparisons");
+  std::vector<bool> bound(r.nvars, false);
+  for (auto& a : r.body) {
+    check_atom(a);
+    for (auto& t : a.t)
+      if (t.var) bound[t.v] = true;
+  }
+  for (auto& t : r.head.t)
+    if (t.var && !bound[t.v]) throw Error(WCDL_E_UNSAFE_RULE, "head variable not bound by the body");
+  for (auto& c : r.cmps)
+    if ((c.a.var && !bound[c.a.v]) || (c.b.var && !bound[c.b.v]))
+      throw Error(WCDL_E_UNSAFE_RULE, "comparison variable not bound by the body");
+  // Variable count after the repeated-variable rewrite.
+  Rule n = normalize(r);
+  u32 used = 0;
+  std::vector<bool> seen(n.nvars, false);
+  for (auto& a : n.body)
+    for (auto& t : a.t)
+      if (t.var && !seen[t.v]) { seen[t.v] = true; ++used; }
+  if (used > (u32)MAXV) throw Error(WCDL_E_UNSUPPORTED, "more than 8 join variables");
+  if (!r.var_order.empty()) {
+    std::vector<u32> vo = r.var_order, bv;
+    for (u32 v = 0; v < r.nvars; ++v)
+      if (bound[v]) bv.push_back(v);
+    std::sort(vo.begin(), vo.end());
+    if (vo != bv) throw Error(WCDL_E_INVALID, "var_order must list every body variable once");
+  }
+}
+
+Rule from_c(const wcdl_rule* cr) {
+  Rule r;
+  u32 nv = cr->n_vars;
+  auto term = [&](const wcdl_term& t) {
+    Term x;
+    x.var = t.kind == WCDL_VAR;
+    if (t.kind != WCDL_VAR && t.kind != WCDL_CONST) throw Error(WCDL_E_INVALID, "bad term kind");
+    x.v = t.value;
+    if (x.var && t.value + 1 > nv) nv = t.value + 1;
+    return x;
+  };
+  auto atom = [&](const wcdl_atom& a) {
+    Atom x;
+    x.rel = a.rel;
+    if (a.arity && !a.terms) throw Error(WCDL_E_INVALID, "null terms");
+    for (u32 j = 0; j < a.arity; ++j) x.t.push_back(term(a.terms[j]));
+    return x;
+  };
+  r.head = atom(cr->head);
+  if (cr->n_body && !cr->body) throw Error(WCDL_E_INVALID, "null body");
+  for (u32 i = 0; i < cr->n_body; ++i) r.body.push_back(atom(cr->body[i]));
+  if (cr->n_cmp && !cr->cmp) throw Error(WCDL_E_INVALID, "null comparisons");
+  for (u32 i = 0; i < cr->n_cmp; ++i) {
+    const wcdl_cmp& c = cr->cmp[i];
+    Cmp x;
+    Term a = term(c.lhs), b = term(c.rhs);
+    switch (c.op) {
+      case WCDL_LT: x.op = OP_LT; x.a = a; x.b = b; break;
+      case WCDL_LE: x.op = OP_LE; x.a = a; x.b = b; break;
+      case WCDL_NE: x.op = OP_NE; x.a = a; x.b = b; break;
+      case WCDL_GT: x.op = OP_LT; x.a = b; x.b = a; break;
+      case WCDL_GE: x.op = OP_LE; x.a = b; x.b = a; break;
+      default: throw Error(WCDL_E_INVALID, "bad comparison operator");
+    }
+    r.cmps.push_back(x);
+  }
+  r.nvars = nv;
+  if (cr->var_order) r.var_order.assign(cr->var_order, cr->var_order + cr->n_vars);
+  return r;
+}
+
+// Parse rules (and ground facts) from text.
+void parse_rules(Engine* e, const std::string& text, std::vector<Rule>& rules,
+                 std::vector<std::pair<u32, std::vector<u32>>>& facts) {
+  Lexer lx(text);
+  while (!lx.at_end()) {
+    std::map<std::string, u32> vars;
+    Rule r;
+    auto var_id = [&](const std::string& name) {
+      if (name == "_") return r.nvars++;
+      auto it = vars.find(name);
+      if (it == vars.end()) it = vars.emplace(name, r.nvars++).first;
+      return it->second;
+    };
+    auto term = [&]() {
+      Term t;
+      u32 c;
+      int rc = lx.number(c);
+      if (rc < 0) lx.fail("constant does not fit in 32 bits");
+      if (rc > 0) { t.var = false; t.v = c; return t; }
+      std::string id;
+      if (!lx.ident(id)) lx.fail("expected a variable or a constant");
+      t.var = true;
+      t.v = var_id(id);
+      return t;
+    };
+    auto atom_args = [&](Atom& a, const std::string& name) {
+      auto it = e->rel_ids.find(name);
+      if (it == e->rel_ids.end()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation " + name);
+      a.rel = it->second;
+      if (!lx.lit("(")) lx.fail("expected '('");
+      if (!lx.lit(")")) {
+        for (;;) {
+          a.t.push_back(term());
+          if (lx.lit(")")) break;
+          if (!lx.lit(",")) lx.fail("expected ',' or ')'");
+        }
+      }
+      if (a.t.size() != e->rels[a.rel].arity)
+        throw Error(WCDL_E_ARITY, "wrong number of arguments for " + name);
+    };
+    std::string name;
+    if (!lx.ident(name)) lx.fail("expected a relation name");
+    atom_args(r.head, name);
+    if (lx.lit(".")) {
+      std::vector<u32> row;
+      for (auto& t : r.head.t) {
+        if (t.var) throw Error(WCDL_E_UNSAFE_RULE, "a fact must be ground");
+        row.push_back(t.v);
+      }
+      facts.push_back({r.head.rel, row});
+      continue;
+    }
+    if (!lx.lit(":-")) lx.fail("expected ':-' or '.'");
+    for (;;) {
+      size_t save = lx.i;
+      std::string id;
+      bool is_atom = lx.ident(id) && lx.peek("(");
+      if (is_atom) {
+        Atom a;
+        atom_args(a, id);
+        r.body.push_back(a);
+      } else {
+        lx.i = save;
+        Term a = term();
+        Cmp c;
+        bool swap = false;
+        if (lx.lit("<=")) c.op = OP_LE;
+        else if (lx.lit(">=")) { c.op = OP_LE; swap = true; }
+        else if (lx.lit("!=")) c.op = OP_NE;
+        else if (lx.lit("<")) c.op = OP_LT;
+        else if (lx.lit(">")) { c.op = OP_LT; swap = true; }
+        else lx.fail("expected a comparison operator");
+        Term b = term();
+        c.a = swap ? b : a;
+        c.b = swap ? a : b;
+        r.cmps.push_back(c);
+      }
+      if (lx.lit(".")) break;
+      if (!lx.lit(",")) lx.fail("expected ',' or '.'");
+    }
+    validate_rule(e, r);
+    rules.push_back(r);
+  }
+}
+
+// Add facts (canonical-order device columns) to a relation's loaded set.
+void add_facts(Engine* e, u32 rel, const std::vector<const u32*>& dcols, u64 n) {
+  Relation& R = e->rels[rel];
+  if (n == 0) return;
+  Cols s = sort_rows(e, 0, canonical(R.arity), dcols, n, true);
+  if (R.base.n == 0) {
+    R.base = std::move(s);
+  } else {
+    Cols d = difference(e, 0, s, R.base);
+    if (d.n) R.base = merged(e, 0, R.base, d);
+  }
+  sync_all(e);
+}
+
+template <class F>
+wcdl_status guarded(wcdl_engine* e, F&& f) {
+  if (!e) return WCDL_E_INVALID;
+  try {
+    e->err.clear();
+    WCDL_HIP(hipSetDevice(e->cfg.device));
+    f();
+    return WCDL_OK;
+  } catch (const Error& x) {
+    e->err = x.what();
+    return x.code;
+  } catch (const std::bad_alloc&) {
+    e->err = "host allocation failed";
+    return WCDL_E_NOMEM;
+  } catch (const std::exception& x) {
+    e->err = x.what();
+    return WCDL_E_INVALID;
+  }
+}
+
+bool valid_name(const char* s) {
+  if (!s || !*s) return false;
+  if (!(isalpha((unsigned char)s[0]) || s[0] == '_')) return false;
+  for (const char* p = s; *p; ++p)
+    if (!(isalnum((unsigned char)*p) || *p == '_')) return false;
+  return true;
+}
+
+u32 declare(Engine* e, const std::string& name, u32 arity) {
+  if (!valid_name(name.c_str())) throw Error(WCDL_E_INVALID, "bad relation name");
+  if (arity == 0 || arity > (u32)MAXA) throw Error(WCDL_E_UNSUPPORTED, "arity must be 1..6");
+  if (e->rel_ids.count(name)) throw Error(WCDL_E_INVALID, "relation " + name + " already declared");
+  Relation R;
+  R.name = name;
+  R.arity = arity;
+  R.base = empty_cols(arity, canonical(arity));
+  R.full = empty_cols(arity, canonical(arity));
+  u32 id = (u32)e->rels.size();
+  e->rels.push_back(std::move(R));
+  e->rel_ids[name] = id;
+  return id;
+}
+
+}  // namespace
+}  // namespace wcdl
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+using namespace wcdl;
+
+extern "C" {
+
+void wcdl_config_default(wcdl_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+}
+
+wcdl_status wcdl_create(const wcdl_config* cfg, wcdl_engine** out) {
+  if (!out) return WCDL_E_INVALID;
+  *out = nullptr;
+  auto* e = new (std::nothrow) wcdl_engine();
+  if (!e) return WCDL_E_NOMEM;
+  if (cfg) e->cfg = *cfg;
+  wcdl_status st = guarded(e, [&] {
+    if (e->cfg.n_streams && e->cfg.streams) {
+      for (u32 i = 0; i < e->cfg.n_streams; ++i) e->streams.push_back((hipStream_t)e->cfg.streams[i]);
+    } else {
+      e->own_streams = true;
+      for (int i = 0; i < 4; ++i) {
+        hipStream_t s;
+        WCDL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        e->streams.push_back(s);
+      }
+    }
+    e->cfg.streams = nullptr;
+    e->mem.reset(new DeviceMemory(e->cfg.alloc, e->streams[0]));
+  });
+  if (st != WCDL_OK) {
+    std::fprintf(stderr, "wcdl_create: %s\n", e->err.c_str());
+    delete e;
+    return st;
+  }
+  *out = e;
+  return WCDL_OK;
+}
+
+void wcdl_destroy(wcdl_engine* e) {
+  if (!e) return;
+  (void)hipSetDevice(e->cfg.device);
+  for (auto s : e->streams) (void)hipStreamSynchronize(s);
+  e->rels.clear();
+  e->mem.reset();
+  if (e->own_streams)
+    for (auto s : e->streams) (void)hipStreamDestroy(s);
+  delete e;
+}
+
+const char* wcdl_last_error(const wcdl_engine* e) { return e ? e->err.c_str() : "null engine"; }
+
+wcdl_status wcdl_declare_relation(wcdl_engine* e, const char* name, uint32_t arity,
+                                  uint32_t* rel_id) {
+  return guarded(e, [&] {
+    if (!name) throw Error(WCDL_E_INVALID, "null name");
+    u32 id = declare(e, name, arity);
+    if (rel_id) *rel_id = id;
+  });
+}
+
+wcdl_status wcdl_relation_id(const wcdl_engine* ce, const char* name, uint32_t* rel_id) {
+  auto* e = const_cast<wcdl_engine*>(ce);
+  return guarded(e, [&] {
+    if (!name || !rel_id) throw Error(WCDL_E_INVALID, "null argument");
+    auto it = e->rel_ids.find(name);
+    if (it == e->rel_ids.end()) throw Error(WCDL_E_UNKNOWN_REL, std::string("unknown relation ") + name);
+    *rel_id = it->second;
+  });
+}
+
+wcdl_status wcdl_load_columns(wcdl_engine* e, uint32_t rel, const uint32_t* const* cols,
+                              uint64_t n_rows, int on_device) {
+  return guarded(e, [&] {
+    if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
+    const u32 k = e->rels[rel].arity;
+    if (n_rows == 0) return;
+    if (!cols) throw Error(WCDL_E_INVALID, "null columns");
+    for (u32 j = 0; j < k; ++j)
+      if (!cols[j]) throw Error(WCDL_E_INVALID, "null column pointer");
+    std::vector<DBuf<u32>> tmp;
+    std::vector<const u32*> dp;
+    for (u32 j = 0; j < k; ++j) {
+      tmp.emplace_back(e->mem.get(), n_rows);
+      WCDL_HIP(hipMemcpyAsync(tmp.back().get(), cols[j], n_rows * sizeof(u32),
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              e->streams[0]));
+      dp.push_back(tmp.back().get());
+    }
+    add_facts(e, rel, dp, n_rows);
+  });
+}
+
+wcdl_status wcdl_clear_relation(wcdl_engine* e, uint32_t rel) {
+  return guarded(e, [&] {
+    if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
+    Relation& R = e->rels[rel];
+    R.base = empty_cols(R.arity, canonical(R.arity));
+    R.full = empty_cols(R.arity, canonical(R.arity));
+    R.full_ord.clear();
+    R.delta_ord.clear();
+  });
+}
+
+wcdl_status wcdl_add_rule(wcdl_engine* e, const wcdl_rule* rule, uint32_t* rule_id) {
+  return guarded(e, [&] {
+    if (!rule) throw Error(WCDL_E_INVALID, "null rule");
+    Rule r = from_c(rule);
+    validate_rule(e, r);
+    e->rules.push_back(r);
+    if (rule_id) *rule_id = (u32)e->rules.size() - 1;
+  });
+}
+
+wcdl_status wcdl_add_rules_text(wcdl_engine* e, const char* text) {
+  return guarded(e, [&] {
+    if (!text) throw Error(WCDL_E_INVALID, "null text");
+    std::vector<Rule> rules;
+    std::vector<std::pair<u32, std::vector<u32>>> facts;
+    parse_rules(e, text, rules, facts);
+    for (auto& r : rules) e->rules.push_back(r);
+    // Ground facts: group by relation and load.
+    std::map<u32, std::vector<std::vector<u32>>> by_rel;
+    for (auto& f : facts) by_rel[f.first].push_back(f.second);
+    for (auto& kv : by_rel) {
+      const u32 k = e->rels[kv.first].arity;
+      const u64 n = kv.second.size();
+      std::vector<std::vector<u32>> colv(k, std::vector<u32>(n));
+      for (u64 i = 0; i < n; ++i)
+        for (u32 j = 0; j < k; ++j) colv[j][i] = kv.second[i][j];
+      std::vector<DBuf<u32>> tmp;
+      std::vector<const u32*> dp;
+      for (u32 j = 0; j < k; ++j) {
+        tmp.emplace_back(e->mem.get(), n);
+        WCDL_HIP(hipMemcpy(tmp.back().get(), colv[j].data(), n * sizeof(u32), hipMemcpyHostToDevice));
+        dp.push_back(tmp.back().get());
+      }
+      add_facts(e, kv.first, dp, n);
+    }
+  });
+}
+
+wcdl_status wcdl_rule_count(const wcdl_engine* ce, uint32_t* n) {
+  auto* e = const_cast<wcdl_engine*>(ce);
+  return guarded(e, [&] {
+    if (!n) throw Error(WCDL_E_INVALID, "null argument");
+    *n = (u32)e->rules.size();
+  });
+}
+
+wcdl_status wcdl_split_rule(wcdl_engine* e, uint32_t rule_id, const uint32_t* atom_idx, uint32_t n,
+                            uint32_t* helper_rel) {
+  return guarded(e, [&] {
+    if (rule_id >= e->rules.size()) throw Error(WCDL_E_INVALID, "unknown rule id");
+    if (!atom_idx || n == 0) throw Error(WCDL_E_INVALID, "no atoms selected");
+    Rule r = e->rules[rule_id];
+    std::set<u32> sel(atom_idx, atom_idx + n);
+    if (sel.size() != n) throw Error(WCDL_E_INVALID, "repeated atom index");
+    for (u32 a : sel)
+      if (a >= r.body.size()) throw Error(WCDL_E_INVALID, "atom index out of range");
+    if (sel.size() >= r.body.size()) throw Error(WCDL_E_INVALID, "must keep at least one atom");
+    std::set<u32> inner;  // variables of the selected atoms
+    for (u32 a : sel)
+      for (auto& t : r.body[a].t)
+        if (t.var) inner.insert(t.v);
+    std::set<u32> outer;  // variables used elsewhere
+    for (u32 a = 0; a < r.body.size(); ++a)
+      if (!sel.count(a))
+        for (auto& t : r.body[a].t)
+          if (t.var) outer.insert(t.v);
+    for (auto& t : r.head.t)
+      if (t.var) outer.insert(t.v);
+    std::vector<Cmp> helper_cmps, rest_cmps;
+    for (auto& c : r.cmps) {
+      bool in_a = !c.a.var || inner.count(c.a.v), in_b = !c.b.var || inner.count(c.b.v);
+      bool only_inner = in_a && in_b && ((c.a.var && !outer.count(c.a.v)) || (c.b.var && !outer.count(c.b.v)));
+      if (in_a && in_b && only_inner) helper_cmps.push_back(c);
+      else {
+        rest_cmps.push_back(c);
+        if (c.a.var) outer.insert(c.a.v);
+        if (c.b.var) outer.insert(c.b.v);
+      }
+    }
+    std::vector<u32> shared;  // in order of first occurrence in the selected atoms
+    for (u32 a : sel)
+      for (auto& t : r.body[a].t)
+        if (t.var && outer.count(t.v) && std::find(shared.begin(), shared.end(), t.v) == shared.end())
+          shared.push_back(t.v);
+    if (shared.empty()) throw Error(WCDL_E_UNSUPPORTED, "selected atoms share no variable with the rule");
+    if (shared.size() > (size_t)MAXA) throw Error(WCDL_E_UNSUPPORTED, "helper relation would exceed arity 6");
+    std::string hname = e->rels[r.head.rel].name + "__h" + std::to_string(e->helper_count);
+    while (e->rel_ids.count(hname)) hname += "_";
+    Rule helper, consumer;
+    helper.nvars = consumer.nvars = r.nvars;
+    u32 hid = (u32)e->rels.size();
+    helper.head.rel = hid;
+    for (u32 v : shared) helper.head.t.push_back(Term{true, v});
+    for (u32 a : sel) helper.body.push_back(r.body[a]);
+    helper.cmps = helper_cmps;
+    consumer.head = r.head;
+    for (u32 a = 0; a < r.body.size(); ++a)
+      if (!sel.count(a)) consumer.body.push_back(r.body[a]);
+    consumer.body.push_back(helper.head);
+    consumer.cmps = rest_cmps;
+    declare(e, hname, (u32)shared.size());
+    try {
+      validate_rule(e, helper);
+      validate_rule(e, consumer);
+    } catch (...) {
+      e->rel_ids.erase(hname);
+      e->rels.pop_back();
+      throw;
+    }
+    e->helper_count++;
+    e->rules[rule_id] = consumer;
+    e->rules.push_back(helper);
+    if (helper_rel) *helper_rel = hid;
+  });
+}
+
+wcdl_status wcdl_run(wcdl_engine* e, wcdl_run_stats* stats) {
+  return guarded(e, [&] { run_program(e, stats); });
+}
+
+wcdl_status wcdl_relation_size(const wcdl_engine* ce, uint32_t rel, uint64_t* n_rows) {
+  auto* e = const_cast<wcdl_engine*>(ce);
+  return guarded(e, [&] {
+    if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
+    if (!n_rows) throw Error(WCDL_E_INVALID, "null argument");
+    const Relation& R = e->rels[rel];
+    *n_rows = R.full.n ? R.full.n : R.base.n;
+  });
+}
+
+wcdl_status wcdl_read_columns(const wcdl_engine* ce, uint32_t rel, uint32_t* const* cols_out,
+                              uint64_t capacity, uint64_t* n_written, int on_device) {
+  auto* e = const_cast<wcdl_engine*>(ce);
+  return guarded(e, [&] {
+    if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
+    const Relation& R = e->rels[rel];
+    const Cols& src = R.full.n ? R.full : R.base;
+    u64 n = std::min<u64>(src.n, capacity);
+    if (n && !cols_out) throw Error(WCDL_E_INVALID, "null output columns");
+    for (u32 j = 0; j < R.arity && n; ++j) {
+      if (!cols_out[j]) throw Error(WCDL_E_INVALID, "null output column");
+      WCDL_HIP(hipMemcpyAsync(cols_out[j], src.col[j].get(), n * sizeof(u32),
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                              e->streams[0]));
+    }
+    WCDL_HIP(hipStreamSynchronize(e->streams[0]));
+    if (n_written) *n_written = n;
+  });
+}
+
+wcdl_status wcdl_delta_sizes(const wcdl_engine* ce, uint32_t rel, uint64_t* out, uint64_t cap,
+                             uint64_t* count) {
+  auto* e = const_cast<wcdl_engine*>(ce);
+  return guarded(e, [&] {
+    if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
+    const auto& d = e->rels[rel].delta_sizes;
+    for (u64 i = 0; i < d.size() && i < cap && out; ++i) out[i] = d[i];
+    if (count) *count = d.size();
+  });
+}
+
+void wcdl_work_slice(uint64_t T, uint64_t p, uint64_t b, uint64_t* b_s, uint64_t* b_e) {
+  const uint64_t s = ceil_div(T, p);
+  uint64_t lo = b * s;
+  if (lo > T) lo = T;
+  uint64_t hi = lo + s < T ? lo + s : T;
+  if (b_s) *b_s = lo;
+  if (b_e) *b_e = hi;
+}
+
+uint64_t wcdl_owner_key(const uint64_t* C, uint64_t K, uint64_t g) { return owner_key(C, 0, K, g); }
+
+void wcdl_decode_unit(const uint64_t* C, uint64_t K, const uint32_t* d2, uint64_t g, uint64_t* key,
+                      uint64_t* i1, uint64_t* i2) {
+  const uint64_t k = owner_key(C, 0, K, g);
+  const uint64_t local = g - (k ? C[k - 1] : 0);
+  if (key) *key = k;
+  if (k < K && d2[k]) {
+    if (i1) *i1 = local / d2[k];
+    if (i2) *i2 = local % d2[k];
+  }
+}
+
+}  // extern "C"

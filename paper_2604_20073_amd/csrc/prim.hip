@@ -1,0 +1,523 @@
+// Data-parallel primitives of the relation store, written for gfx950
+// (wave64, 160 KB LDS per CU): prefix scans, LSD radix sort of multi-column
+// rows, adjacent-duplicate removal, sorted set difference and the merge of
+// two disjoint sorted runs.  The paper's pipeline relies on a memory-bound
+// radix sort for Build Index and a single-pass merge for Merge (Sec. 4);
+// these are this engine's own versions of both.
+
+#include "wcdl_internal.h"
+
+namespace wcdl {
+namespace {
+
+constexpr int WG = 256;        // threads per workgroup (4 waves of 64)
+constexpr int SCAN_IPT = 8;    // items per thread in scans
+constexpr int SCAN_TILE = WG * SCAN_IPT;
+constexpr int RS_IPT = 16;     // keys per thread in radix passes
+constexpr int RS_TILE = WG * RS_IPT;  // 4096 keys per tile
+constexpr int SEARCH_IPT = 4;  // rows per thread in tiled searches
+constexpr int SEARCH_TILE = WG * SEARCH_IPT;
+
+struct ColsIn { const u32* c[MAXA]; };
+struct ColsOut { u32* c[MAXA]; };
+
+ColsIn cols_in(u32 k, const u32* const* p) {
+  ColsIn a{};
+  for (u32 j = 0; j < k; ++j) a.c[j] = p[j];
+  return a;
+}
+ColsOut cols_out(u32 k, u32* const* p) {
+  ColsOut a{};
+  for (u32 j = 0; j < k; ++j) a.c[j] = p[j];
+  return a;
+}
+
+u32 grid_for(u64 n, u64 per_block) {
+  u64 g = ceil_div(n, per_block);
+  if (g > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "grid too large");
+  return (u32)(g ? g : 1);
+}
+
+// ---- wave / block scans ---------------------------------------------------
+
+__device__ inline u64 shfl_up_u64(u64 x, int d) {
+  u32 lo = __shfl_up((u32)x, d, 64);
+  u32 hi = __shfl_up((u32)(x >> 32), d, 64);
+  return ((u64)hi << 32) | lo;
+}
+
+__device__ inline u64 wave_incl_scan(u64 x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    u64 y = shfl_up_u64(x, d);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan across the 256 threads; *total gets the block sum.
+__device__ inline u64 block_excl_scan(u64 x, u64* sh, u64* total) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  u64 inc = wave_incl_scan(x);
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  u64 off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < WG / 64; ++i) {
+    u64 s = sh[i];
+    if (i < w) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - x;
+}
+
+template <class T>
+__global__ __launch_bounds__(WG) void k_scan_reduce(const T* in, u64 n, u64* bsum) {
+  __shared__ u64 sh[WG / 64];
+  u64 base = (u64)blockIdx.x * SCAN_TILE + (u64)threadIdx.x * SCAN_IPT;
+  u64 s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; ++i)
+    if (base + i < n) s += (u64)in[base + i];
+  u64 tot;
+  block_excl_scan(s, sh, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// out = exclusive (or inclusive) scan of in, offset by bpre[block].
+template <class T>
+__global__ __launch_bounds__(WG) void k_scan_down(const T* in, u64* out, u64 n, const u64* bpre,
+                                                  int inclusive, u64* d_total) {
+  __shared__ u64 sh[WG / 64];
+  u64 base = (u64)blockIdx.x * SCAN_TILE + (u64)threadIdx.x * SCAN_IPT;
+  u64 v[SCAN_IPT];
+  u64 s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; ++i) {
+    v[i] = (base + i < n) ? (u64)in[base + i] : 0;
+    s += v[i];
+  }
+  u64 tot;
+  u64 run = block_excl_scan(s, sh, &tot) + (bpre ? bpre[blockIdx.x] : 0);
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; ++i) {
+    if (base + i < n) out[base + i] = inclusive ? run + v[i] : run;
+    run += v[i];
+  }
+  if (d_total && !bpre && threadIdx.x == 0) *d_total = tot;
+}
+
+__global__ void k_set_total(const u64* bpre, const u64* bsum, u64 nb, u64* d_total) {
+  *d_total = bpre[nb - 1] + bsum[nb - 1];
+}
+
+template <class T>
+void scan_impl(Ctx c, const T* in, u64* out, u64 n, u64* d_total, int inclusive) {
+  if (n == 0) {
+    if (d_total) fill_u64(c, d_total, 1, 0);
+    return;
+  }
+  u64 nb = ceil_div(n, SCAN_TILE);
+  if (nb == 1) {
+    k_scan_down<T><<<1, WG, 0, c.s>>>(in, out, n, nullptr, inclusive, d_total);
+    WCDL_HIP(hipGetLastError());
+    return;
+  }
+  DBuf<u64> bsum(c.mem, nb), bpre(c.mem, nb);
+  k_scan_reduce<T><<<grid_for(nb, 1), WG, 0, c.s>>>(in, n, bsum.get());
+  WCDL_HIP(hipGetLastError());
+  scan_impl<u64>(c, bsum.get(), bpre.get(), nb, nullptr, 0);
+  k_scan_down<T><<<grid_for(nb, 1), WG, 0, c.s>>>(in, out, n, bpre.get(), inclusive, nullptr);
+  WCDL_HIP(hipGetLastError());
+  if (d_total) {
+    k_set_total<<<1, 1, 0, c.s>>>(bpre.get(), bsum.get(), nb, d_total);
+    WCDL_HIP(hipGetLastError());
+  }
+}
+
+// ---- fills ---------------------------------------------------------------
+
+template <class T>
+__global__ void k_fill(T* p, u64 n, T v) {
+  u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  u64 stride = (u64)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_copy(u32* dst, const u32* src, u64 n) {
+  u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  u64 stride = (u64)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+u32 stream_grid(u64 n) {
+  u64 g = ceil_div(n, WG);
+  return (u32)(g < 65536 ? (g ? g : 1) : 65536);
+}
+
+// ---- column OR (bit width of keys) ---------------------------------------
+
+__global__ __launch_bounds__(WG) void k_col_or(ColsIn a, u32 k, u64 n, u32* d_or) {
+  u64 stride = (u64)gridDim.x * WG;
+  for (u32 j = 0; j < k; ++j) {
+    u32 acc = 0;
+    for (u64 i = (u64)blockIdx.x * WG + threadIdx.x; i < n; i += stride) acc |= a.c[j][i];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc |= __shfl_xor(acc, d, 64);
+    if ((threadIdx.x & 63) == 0 && acc) atomicOr(&d_or[j], acc);
+  }
+}
+
+// ---- radix sort ------------------------------------------------------------
+//
+// One pass = (digit histogram per tile) -> (exclusive scan, digit-major over
+// tiles) -> (stable scatter).  The scatter ranks keys inside a tile with
+// 64-lane ballots: the lanes holding the same 8-bit digit are found with
+// eight ballots, the lowest of them updates a per-wave digit counter, and
+// the tile is then written through LDS in digit order so global writes form
+// contiguous runs.
+
+__device__ inline u64 lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Lanes (among `valid` ones) whose digit equals this lane's digit.
+__device__ inline u64 match_digit(u32 d, bool valid) {
+  u64 m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    bool bit = (d >> b) & 1u;
+    u64 bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(WG) void k_rs_hist(const u32* key, u64 n, u32 shift, u32* counts,
+                                                u32 ntiles) {
+  __shared__ u32 wcnt[WG / 64][256];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < (WG / 64) * 256; i += WG) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+  const u64 base = (u64)blockIdx.x * RS_TILE + (u64)w * (64 * RS_IPT);
+#pragma unroll 4
+  for (int i = 0; i < RS_IPT; ++i) {
+    u64 idx = base + (u64)i * 64 + lane;
+    bool valid = idx < n;
+    u32 d = valid ? (key[idx] >> shift) & 255u : 0u;
+    u64 m = match_digit(d, valid);
+    if (valid && (m & lanemask_lt()) == 0) wcnt[w][d] += (u32)__popcll(m);
+  }
+  __syncthreads();
+  u32 t = threadIdx.x;
+  u32 s = 0;
+#pragma unroll
+  for (int ww = 0; ww < WG / 64; ++ww) s += wcnt[ww][t];
+  counts[(u64)t * ntiles + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(WG) void k_rs_scatter(ColsIn in, ColsOut out, u32 k, const u32* key,
+                                                   u64 n, u32 shift, const u64* offs, u32 ntiles) {
+  __shared__ u32 wcnt[WG / 64][256];
+  __shared__ u32 dstart[256];
+  __shared__ u64 gofs[256];
+  __shared__ u64 sh[WG / 64];
+  __shared__ u32 tile[RS_TILE];
+  __shared__ uint8_t tdig[RS_TILE];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < (WG / 64) * 256; i += WG) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+  const u64 tbase = (u64)blockIdx.x * RS_TILE;
+  const u64 base = tbase + (u64)w * (64 * RS_IPT);
+  u32 dig[RS_IPT];
+  u32 pos[RS_IPT];
+#pragma unroll
+  for (int i = 0; i < RS_IPT; ++i) {
+    u64 idx = base + (u64)i * 64 + lane;
+    bool valid = idx < n;
+    u32 d = valid ? (key[idx] >> shift) & 255u : 0u;
+    u64 m = match_digit(d, valid);
+    u32 below = (u32)__popcll(m & lanemask_lt());
+    u32 prev = valid ? wcnt[w][d] : 0u;
+    if (valid && below == 0) wcnt[w][d] = prev + (u32)__popcll(m);
+    dig[i] = valid ? d : 256u;
+    pos[i] = prev + below;
+  }
+  __syncthreads();
+  {
+    u32 t = threadIdx.x;
+    u32 c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+    wcnt[0][t] = 0;
+    wcnt[1][t] = c0;
+    wcnt[2][t] = c0 + c1;
+    wcnt[3][t] = c0 + c1 + c2;
+    u64 tot;
+    u64 ds = block_excl_scan((u64)(c0 + c1 + c2 + c3), sh, &tot);
+    dstart[t] = (u32)ds;
+    gofs[t] = offs[(u64)t * ntiles + blockIdx.x];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RS_IPT; ++i) {
+    if (dig[i] < 256u) {
+      pos[i] += dstart[dig[i]] + wcnt[w][dig[i]];
+      tdig[pos[i]] = (uint8_t)dig[i];
+    }
+  }
+  const u32 tn = (u32)((n - tbase) < (u64)RS_TILE ? (n - tbase) : (u64)RS_TILE);
+  for (u32 j = 0; j < k; ++j) {
+    const u32* src = in.c[j];
+    u32* dst = out.c[j];
+#pragma unroll
+    for (int i = 0; i < RS_IPT; ++i)
+      if (dig[i] < 256u) tile[pos[i]] = src[base + (u64)i * 64 + lane];
+    __syncthreads();
+    for (u32 t = threadIdx.x; t < tn; t += WG) {
+      u32 d = tdig[t];
+      dst[gofs[d] + (t - dstart[d])] = tile[t];
+    }
+    __syncthreads();
+  }
+}
+
+// ---- row comparisons and tiled searches ------------------------------------
+
+__device__ inline void load_row(const ColsIn& a, u32 k, u64 i, u32 (&r)[MAXA]) {
+#pragma unroll
+  for (int j = 0; j < MAXA; ++j) r[j] = (j < (int)k) ? a.c[j][i] : 0u;
+}
+
+// Is row i of b lexicographically less than key?
+__device__ inline bool row_less(const ColsIn& b, u32 k, u64 i, const u32 (&key)[MAXA]) {
+#pragma unroll
+  for (int j = 0; j < MAXA; ++j) {
+    if (j < (int)k) {
+      u32 x = b.c[j][i];
+      if (x != key[j]) return x < key[j];
+    }
+  }
+  return false;
+}
+
+__device__ inline bool row_equal(const ColsIn& b, u32 k, u64 i, const u32 (&key)[MAXA]) {
+#pragma unroll
+  for (int j = 0; j < MAXA; ++j)
+    if (j < (int)k && b.c[j][i] != key[j]) return false;
+  return true;
+}
+
+__device__ inline u64 row_lower_bound(const ColsIn& b, u32 k, u64 lo, u64 hi,
+                                      const u32 (&key)[MAXA]) {
+  while (lo < hi) {
+    u64 mid = lo + ((hi - lo) >> 1);
+    if (row_less(b, k, mid, key)) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Range of b that can hold the rows of a's tile [t0, t1): [lb(a[t0]), lb(a[t1-1]) + 1).
+__device__ inline void tile_window(const ColsIn& a, const ColsIn& b, u32 k, u64 t0, u64 t1,
+                                   u64 nb, u64* wlo, u64* whi) {
+  u32 key[MAXA];
+  load_row(a, k, t0, key);
+  u64 lo = row_lower_bound(b, k, 0, nb, key);
+  load_row(a, k, t1 - 1, key);
+  u64 hi = row_lower_bound(b, k, lo, nb, key);
+  *wlo = lo;
+  *whi = hi < nb ? hi + 1 : nb;
+}
+
+__global__ __launch_bounds__(WG) void k_adjacent_flags(ColsIn a, u32 k, u64 n, u32* flags) {
+  u64 i = (u64)blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  u32 f = 1;
+  if (i > 0) {
+    f = 0;
+    for (u32 j = 0; j < k; ++j)
+      if (a.c[j][i] != a.c[j][i - 1]) { f = 1; break; }
+  }
+  flags[i] = f;
+}
+
+__global__ __launch_bounds__(WG) void k_compact(ColsIn a, ColsOut o, u32 k, u64 n,
+                                                const u32* flags, const u64* pos) {
+  u64 i = (u64)blockIdx.x * WG + threadIdx.x;
+  if (i >= n || !flags[i]) return;
+  u64 p = pos[i];
+  for (u32 j = 0; j < k; ++j) o.c[j][p] = a.c[j][i];
+}
+
+__global__ __launch_bounds__(WG) void k_absent_flags(ColsIn a, ColsIn b, u32 k, u64 na, u64 nb,
+                                                     u32* flags) {
+  __shared__ u64 win[2];
+  const u64 t0 = (u64)blockIdx.x * SEARCH_TILE;
+  const u64 t1 = (t0 + SEARCH_TILE < na) ? t0 + SEARCH_TILE : na;
+  if (threadIdx.x == 0) tile_window(a, b, k, t0, t1, nb, &win[0], &win[1]);
+  __syncthreads();
+  const u64 wlo = win[0], whi = win[1];
+  for (u64 i = t0 + threadIdx.x; i < t1; i += WG) {
+    u32 key[MAXA];
+    load_row(a, k, i, key);
+    u64 p = row_lower_bound(b, k, wlo, whi, key);
+    flags[i] = (p < whi && row_equal(b, k, p, key)) ? 0u : 1u;
+  }
+}
+
+// Each row of `a` goes to its own index plus the number of rows of `b`
+// below it (runs are disjoint, so that count is exact).
+__global__ __launch_bounds__(WG) void k_merge_place(ColsIn a, ColsIn b, ColsOut o, u32 k, u64 na,
+                                                    u64 nb) {
+  __shared__ u64 win[2];
+  const u64 t0 = (u64)blockIdx.x * SEARCH_TILE;
+  const u64 t1 = (t0 + SEARCH_TILE < na) ? t0 + SEARCH_TILE : na;
+  if (threadIdx.x == 0) {
+    if (nb) tile_window(a, b, k, t0, t1, nb, &win[0], &win[1]);
+    else win[0] = win[1] = 0;
+  }
+  __syncthreads();
+  const u64 wlo = win[0], whi = win[1];
+  for (u64 i = t0 + threadIdx.x; i < t1; i += WG) {
+    u32 key[MAXA];
+    load_row(a, k, i, key);
+    u64 p = i + row_lower_bound(b, k, wlo, whi, key);
+#pragma unroll
+    for (int j = 0; j < MAXA; ++j)
+      if (j < (int)k) o.c[j][p] = key[j];
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+void scan_u32_excl(Ctx c, const u32* in, u64* out, u64 n, u64* d_total) {
+  scan_impl<u32>(c, in, out, n, d_total, 0);
+}
+void scan_u64_excl(Ctx c, const u64* in, u64* out, u64 n, u64* d_total) {
+  scan_impl<u64>(c, in, out, n, d_total, 0);
+}
+void scan_u64_incl(Ctx c, const u64* in, u64* out, u64 n, u64* d_total) {
+  scan_impl<u64>(c, in, out, n, d_total, 1);
+}
+
+void fill_u32(Ctx c, u32* p, u64 n, u32 v) {
+  if (!n) return;
+  k_fill<u32><<<stream_grid(n), WG, 0, c.s>>>(p, n, v);
+  WCDL_HIP(hipGetLastError());
+}
+void fill_u64(Ctx c, u64* p, u64 n, u64 v) {
+  if (!n) return;
+  k_fill<u64><<<stream_grid(n), WG, 0, c.s>>>(p, n, v);
+  WCDL_HIP(hipGetLastError());
+}
+void copy_u32(Ctx c, u32* dst, const u32* src, u64 n) {
+  if (!n) return;
+  k_copy<<<stream_grid(n), WG, 0, c.s>>>(dst, src, n);
+  WCDL_HIP(hipGetLastError());
+}
+
+void column_or(Ctx c, u32 k, const u32* const* cols, u64 n, u32* d_or) {
+  fill_u32(c, d_or, k, 0);
+  if (!n) return;
+  u32 g = stream_grid(n);
+  if (g > 4096) g = 4096;
+  k_col_or<<<g, WG, 0, c.s>>>(cols_in(k, cols), k, n, d_or);
+  WCDL_HIP(hipGetLastError());
+}
+
+void radix_sort_rows(Ctx c, u32 k, const u32* const* in_cols, u32* const* out_cols, u64 n,
+                     const u32* col_bits) {
+  if (k == 0 || k > (u32)MAXA) throw Error(WCDL_E_UNSUPPORTED, "radix sort arity");
+  // Digit passes from the least significant digit of the last column up.
+  std::vector<std::pair<u32, u32>> passes;  // (column, shift)
+  for (int j = (int)k - 1; j >= 0; --j)
+    for (u32 sh = 0; sh < col_bits[j]; sh += 8) passes.push_back({(u32)j, sh});
+  if (n <= 1 || passes.empty()) {
+    for (u32 j = 0; j < k; ++j)
+      if (n) copy_u32(c, out_cols[j], in_cols[j], n);
+    return;
+  }
+  const u32 ntiles = grid_for(n, RS_TILE);
+  DBuf<u32> counts(c.mem, (u64)256 * ntiles);
+  DBuf<u64> offs(c.mem, (u64)256 * ntiles);
+  std::vector<DBuf<u32>> tmp;
+  for (u32 j = 0; j < k; ++j) tmp.emplace_back(c.mem, n);
+  const size_t P = passes.size();
+  const u32* const* src = in_cols;
+  std::vector<const u32*> src_v(k);
+  std::vector<u32*> dst_v(k);
+  for (size_t p = 0; p < P; ++p) {
+    bool to_out = ((P - 1 - p) % 2) == 0;
+    for (u32 j = 0; j < k; ++j) dst_v[j] = to_out ? out_cols[j] : tmp[j].get();
+    const u32* key = src[passes[p].first];
+    k_rs_hist<<<ntiles, WG, 0, c.s>>>(key, n, passes[p].second, counts.get(), ntiles);
+    WCDL_HIP(hipGetLastError());
+    scan_u32_excl(c, counts.get(), offs.get(), (u64)256 * ntiles, nullptr);
+    k_rs_scatter<<<ntiles, WG, 0, c.s>>>(cols_in(k, src), cols_out(k, dst_v.data()), k, key, n,
+                                         passes[p].second, offs.get(), ntiles);
+    WCDL_HIP(hipGetLastError());
+    for (u32 j = 0; j < k; ++j) src_v[j] = dst_v[j];
+    src = src_v.data();
+  }
+}
+
+u64 unique_rows(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32* const* out_cols) {
+  if (n == 0) return 0;
+  DBuf<u32> flags(c.mem, n);
+  DBuf<u64> pos(c.mem, n), total(c.mem, 1);
+  ColsIn a = cols_in(k, in_cols);
+  k_adjacent_flags<<<grid_for(n, WG), WG, 0, c.s>>>(a, k, n, flags.get());
+  WCDL_HIP(hipGetLastError());
+  scan_u32_excl(c, flags.get(), pos.get(), n, total.get());
+  k_compact<<<grid_for(n, WG), WG, 0, c.s>>>(a, cols_out(k, out_cols), k, n, flags.get(),
+                                              pos.get());
+  WCDL_HIP(hipGetLastError());
+  u64 h = 0;
+  WCDL_HIP(hipMemcpyAsync(&h, total.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
+  WCDL_HIP(hipStreamSynchronize(c.s));
+  return h;
+}
+
+u64 set_difference(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* b, u64 nb,
+                   u32* const* out) {
+  if (na == 0) return 0;
+  ColsIn A = cols_in(k, a);
+  if (nb == 0) {
+    for (u32 j = 0; j < k; ++j) copy_u32(c, out[j], a[j], na);
+    return na;
+  }
+  DBuf<u32> flags(c.mem, na);
+  DBuf<u64> pos(c.mem, na), total(c.mem, 1);
+  k_absent_flags<<<grid_for(na, SEARCH_TILE), WG, 0, c.s>>>(A, cols_in(k, b), k, na, nb,
+                                                            flags.get());
+  WCDL_HIP(hipGetLastError());
+  scan_u32_excl(c, flags.get(), pos.get(), na, total.get());
+  k_compact<<<grid_for(na, WG), WG, 0, c.s>>>(A, cols_out(k, out), k, na, flags.get(), pos.get());
+  WCDL_HIP(hipGetLastError());
+  u64 h = 0;
+  WCDL_HIP(hipMemcpyAsync(&h, total.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
+  WCDL_HIP(hipStreamSynchronize(c.s));
+  return h;
+}
+
+void merge_disjoint(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* b, u64 nb,
+                    u32* const* out) {
+  ColsIn A = cols_in(k, a), B = cols_in(k, b);
+  ColsOut O = cols_out(k, out);
+  if (na) {
+    k_merge_place<<<grid_for(na, SEARCH_TILE), WG, 0, c.s>>>(A, B, O, k, na, nb);
+    WCDL_HIP(hipGetLastError());
+  }
+  if (nb) {
+    k_merge_place<<<grid_for(nb, SEARCH_TILE), WG, 0, c.s>>>(B, A, O, k, nb, na);
+    WCDL_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace wcdl

@@ -1,0 +1,277 @@
+// Internal declarations shared by the engine's host code and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "wcdl.h"
+
+namespace wcdl {
+
+using u32 = uint32_t;
+using u64 = uint64_t;
+
+constexpr int MAXA = WCDL_MAX_ARITY;  // columns per atom
+constexpr int MAXN = WCDL_MAX_BODY;   // atoms per rule body
+constexpr int MAXV = WCDL_MAX_VARS;   // variables (join levels) per rule
+constexpr int MAXS = MAXN;            // sources per level (one per atom at most)
+constexpr int MAXB = 8;               // value bounds per level
+constexpr int MAXF = 4;               // inequality filters per level
+constexpr u32 NONE = 0xffffffffu;
+
+// ---------------------------------------------------------------------------
+// Errors: thrown inside the library, turned into status codes at the C ABI.
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define WCDL_HIP(call)                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::wcdl::Error(WCDL_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device memory: blocks come from the caller's allocator (or hipMalloc) and
+// are cached by size class.  A freed block becomes reusable only after the
+// next device-wide synchronisation point, so a block still read by work on
+// another stream is never handed out again too early.
+// ---------------------------------------------------------------------------
+class DeviceMemory {
+ public:
+  DeviceMemory(const wcdl_allocator& a, hipStream_t s) : user_(a), stream_(s) {}
+  ~DeviceMemory();
+  void* get(size_t bytes);
+  void put(void* p);
+  void sync_point();  // pending frees become reusable
+  void release_cached();
+  size_t live_bytes() const { return live_bytes_; }
+
+ private:
+  static size_t size_class(size_t bytes);
+  void* raw_alloc(size_t bytes);
+  void raw_free(void* p, size_t bytes);
+  wcdl_allocator user_;
+  hipStream_t stream_;
+  std::multimap<size_t, void*> free_;
+  std::vector<std::pair<void*, size_t>> pending_;
+  std::map<void*, size_t> live_;
+  size_t live_bytes_ = 0;
+};
+
+// Owning handle to a device array of T.
+template <class T>
+class DBuf {
+ public:
+  DBuf() = default;
+  DBuf(DeviceMemory* m, u64 n) : mem_(m), n_(n) {
+    if (n) p_ = static_cast<T*>(m->get(n * sizeof(T)));
+  }
+  ~DBuf() { reset(); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : mem_(o.mem_), p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      reset();
+      mem_ = o.mem_; p_ = o.p_; n_ = o.n_;
+      o.p_ = nullptr; o.n_ = 0;
+    }
+    return *this;
+  }
+  void reset() {
+    if (p_ && mem_) mem_->put(p_);
+    p_ = nullptr;
+    n_ = 0;
+  }
+  T* get() const { return p_; }
+  u64 size() const { return n_; }
+
+ private:
+  DeviceMemory* mem_ = nullptr;
+  T* p_ = nullptr;
+  u64 n_ = 0;
+};
+
+// A relation (or delta) stored as k sorted device columns.  order[j] is the
+// column of the logical relation that this copy holds in position j; rows
+// are sorted lexicographically by position 0, 1, ..., k-1 and unique.
+struct Cols {
+  std::vector<u32> order;
+  std::vector<DBuf<u32>> col;
+  u64 n = 0;
+  u32 arity() const { return (u32)order.size(); }
+  std::vector<const u32*> ptrs() const {
+    std::vector<const u32*> v;
+    for (auto& c : col) v.push_back(c.get());
+    return v;
+  }
+  std::vector<u32*> mptrs() {
+    std::vector<u32*> v;
+    for (auto& c : col) v.push_back(c.get());
+    return v;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Join plan as the kernels see it (one per rule version).  Levels are the
+// join variables x_1..x_m in the chosen order (index 0-based here).  Each
+// body atom is read through a sorted copy whose column order follows the
+// variable order (constants first), so binding the variables level by level
+// narrows each atom to a contiguous row range (Sec. 4: tuples sharing a
+// prefix are contiguous; Sec. 2: attribute-at-a-time evaluation).
+// ---------------------------------------------------------------------------
+struct DOperand {
+  u32 is_var;  // 1: value of the variable at level `v`; 0: constant `v`
+  u32 v;
+};
+
+struct DSource {      // an atom constraining the level's variable
+  const u32* col;     // the atom's column holding this variable
+  u32 atom;           // atom index (range slot)
+  u32 last;           // 1 if no variable column of the atom follows
+};
+
+struct DBound {       // x_level >= opnd + adj (lo) or x_level <= opnd - adj (hi)
+  u32 is_hi;
+  u32 adj;
+  DOperand o;
+};
+
+struct DLevel {
+  u32 nsrc;
+  u32 nbnd;
+  u32 nne;
+  u32 pad_;
+  DSource src[MAXS];
+  DBound bnd[MAXB];
+  DOperand ne[MAXF];      // x_level != operand
+  u32 atom_src[MAXN];     // per atom: its source index at this level, or NONE
+};
+
+struct DPlan {
+  u32 m;                  // number of variables (join depth)
+  u32 natoms;
+  u32 root_src;           // source (at level 0) whose column supplies the root keys
+  u32 head_arity;
+  u32 leaf_fast;          // count pass may sum leaf candidate ranges (single
+                          // distinct-valued source, no filter at the leaf)
+  u32 xprod;              // levels >= 1 are independent single sources
+  DOperand head[MAXA];
+  u32* out[MAXA];         // output columns (materialize)
+  u64 out_rows;           // rows reserved at out[] (writes beyond are refused)
+  u32* err;               // device flag set if a write was refused
+  u64* cand;              // optional: candidates examined (materialize pass)
+  u32 atom_n[MAXN];       // rows in each atom's sorted copy
+  u32 atom_nconst[MAXN];  // leading constant columns of each atom
+  u32 atom_const[MAXN][MAXA];
+  const u32* atom_col[MAXN][MAXA];
+  DLevel lvl[MAXV];
+  // Shared-memory layout of the level buffers (offsets in 32-bit words).
+  u32 cap;                // items per level buffer
+  u32 off_val[MAXV], off_lo[MAXV], off_hi[MAXV], off_drv[MAXV], off_clo[MAXV],
+      off_chi[MAXV], off_pre[MAXV];
+  u32 lds_words;
+};
+
+// Root-level work space (Alg. 1 Phase 1): K root keys U with row starts S
+// (S[K] = end of range) in the root atom's sorted copy, inclusive prefix sums
+// C of the per-key work W, total T.
+struct RootSpace {
+  const u32* U;
+  const u32* S;
+  const u64* C;
+  u64 K;
+  u64 T;
+  const u32* rng0;        // per atom [lo, hi) after constant narrowing (2*MAXN)
+};
+
+// Work partition (Alg. 2): p workgroups; slice = ceil(T/p) units each, or
+// with balance off one root key per workgroup.
+struct Partition {
+  u64 p;
+  u64 slice;
+  u32 balance_off;
+  u32 pad_;
+};
+
+// ---------------------------------------------------------------------------
+// Host-callable launchers (prim.hip, wcoj.hip).  All are asynchronous on
+// `s` unless noted.
+// ---------------------------------------------------------------------------
+struct Ctx {
+  DeviceMemory* mem;
+  hipStream_t s;
+};
+
+// Exclusive scan of n values into out (u64); *d_total (device) = sum.
+void scan_u32_excl(Ctx c, const u32* in, u64* out, u64 n, u64* d_total);
+void scan_u64_excl(Ctx c, const u64* in, u64* out, u64 n, u64* d_total);
+// Inclusive scan u64 -> u64.
+void scan_u64_incl(Ctx c, const u64* in, u64* out, u64 n, u64* d_total);
+
+// Radix sort of rows (LSD, 8-bit digits).  in_cols[j] / out_cols[j] are the
+// key columns in significance order (column 0 most significant).  col_bits[j]
+// = number of significant bits of column j (values must be < 2^bits).
+void radix_sort_rows(Ctx c, u32 k, const u32* const* in_cols, u32* const* out_cols, u64 n,
+                     const u32* col_bits);
+// OR of all values of each column (device results in d_or[k]).
+void column_or(Ctx c, u32 k, const u32* const* cols, u64 n, u32* d_or);
+
+// Unique adjacent rows of a sorted input; returns the count (synchronises).
+u64 unique_rows(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32* const* out_cols);
+// Rows of sorted-unique A absent from sorted-unique B; returns count (syncs).
+u64 set_difference(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* b, u64 nb,
+                   u32* const* out);
+// Merge two disjoint sorted-unique runs into out (na + nb rows).
+void merge_disjoint(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* b, u64 nb,
+                    u32* const* out);
+// Fill helpers.
+void fill_u32(Ctx c, u32* p, u64 n, u32 v);
+void fill_u64(Ctx c, u64* p, u64 n, u64 v);
+void copy_u32(Ctx c, u32* dst, const u32* src, u64 n);
+
+// WCOJ (wcoj.hip).
+void join_init_ranges(Ctx c, const DPlan* d_plan, u32 natoms, u32* d_rng0);
+// Root keys of column `col` in rows [rng0[2a], rng0[2a+1]) of atom a, in two
+// asynchronous steps: flags + scan (count of keys into *d_K), then, once K
+// is known on the host, compaction into U (K values) and S (K+1 row starts).
+void join_root_flags(Ctx c, const u32* col, const u32* d_rng0, u32 atom, u32 n_rows, u32* flags,
+                     u64* pos, u64* d_K);
+void join_root_compact(Ctx c, const u32* col, const u32* d_rng0, u32 atom, u32 n_rows,
+                       const u32* flags, const u64* pos, u64 K, u32* U, u32* S);
+// Per-key work W (Alg. 1 Phase 1).  For cross-product plans also writes
+// per-key (lo, size) of every level >= 1 into klo/kd ([m][K]).
+void join_histogram(Ctx c, const DPlan* d_plan, const RootSpace& rs, u64* W, u32* klo, u32* kd,
+                    u32 m);
+// Count (mode 0) or materialize (mode 1) over workgroups [wg0, wg0+nwg).
+void join_run(Ctx c, const DPlan* d_plan, const RootSpace& rs, const Partition& part,
+              u32 lds_bytes, int mode, u64* counts, const u64* offsets, u64 wg0, u64 nwg);
+// Cross-product decode path: writes T rows directly.
+void join_xprod(Ctx c, const DPlan* d_plan, const RootSpace& rs, const u32* klo, const u32* kd,
+                u32 m);
+
+}  // namespace wcdl
+
+// Shared by host and device: the work-slice arithmetic of Alg. 2.
+namespace wcdl {
+__host__ __device__ inline u64 ceil_div(u64 a, u64 b) { return b ? (a + b - 1) / b : 0; }
+
+// First index k in [lo, hi) with C[k] > g (C nondecreasing); hi if none.
+__host__ __device__ inline u64 owner_key(const u64* C, u64 lo, u64 hi, u64 g) {
+  while (lo < hi) {
+    u64 mid = lo + ((hi - lo) >> 1);
+    if (C[mid] <= g) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+}  // namespace wcdl

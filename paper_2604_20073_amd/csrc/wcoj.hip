@@ -1,0 +1,708 @@
+// Work-balanced worst-case-optimal join kernels for gfx950.
+//
+// A rule version is joined attribute at a time (paper Sec. 2, "Join
+// Processing"): the variables x_0..x_{m-1} are bound in a fixed order, and the
+// candidates for x_L are the values of one source atom's column inside its
+// current row range, each kept only if every other atom constraining x_L
+// holds it too (a leapfrog-style seek by binary search inside that atom's
+// range).  Binding a value narrows every constraining atom to the contiguous
+// rows that share the bound prefix (Sec. 4, flat sorted columns).
+//
+// Work balance follows Sec. 5 (Alg. 1 and Alg. 2): the histogram kernel
+// gives every distinct root key k its work W[k] (the number of level-1
+// candidates under it; for cross-product plans the product of the fan-outs),
+// an inclusive prefix sum C flattens all work into [0, T), and workgroup b
+// owns units [b*ceil(T/p), (b+1)*ceil(T/p)).  A heavy key is thereby split
+// across workgroups.  Inside a workgroup, the deeper levels are expanded
+// breadth-first in chunks of 256 candidates held in LDS buffers (one per
+// level) and drained depth-first, so each lane checks one candidate at a
+// time whatever the fan-out of the item it came from; this is the
+// wavefront-cooperative form of the inner intersection on this GPU.
+//
+// Count and materialize run the same traversal (Sec. 4, two-phase
+// deterministic allocation): count writes one total per workgroup, an
+// exclusive scan turns totals into offsets, and materialize writes every
+// workgroup's rows at its offset in traversal order, so the output is
+// deterministic and, in variable order, lexicographically sorted.
+
+#include "wcdl_internal.h"
+
+namespace wcdl {
+namespace {
+
+constexpr int WG = 256;
+constexpr u32 UMAX = 0xffffffffu;
+
+__device__ inline u32 lower_bound_u32(const u32* col, u32 lo, u32 hi, u32 v) {
+  while (lo < hi) {
+    u32 mid = lo + ((hi - lo) >> 1);
+    if (col[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ inline u32 upper_bound_u32(const u32* col, u32 lo, u32 hi, u32 v) {
+  while (lo < hi) {
+    u32 mid = lo + ((hi - lo) >> 1);
+    if (col[mid] <= v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// First index >= lo in [lo, hi) with col > v, by galloping from lo (runs of
+// equal values are usually short).
+__device__ inline u32 gallop_past(const u32* col, u32 lo, u32 hi, u32 v) {
+  u32 a = lo;
+  u64 b = lo, step = 1;
+  while (b < hi && col[b] <= v) {
+    a = (u32)b + 1;
+    b = (u64)a + step;
+    step <<= 1;
+  }
+  return upper_bound_u32(col, a, b < hi ? (u32)b : hi, v);
+}
+
+// Eight values held in named registers.  A plain array indexed with a lane-
+// varying index would be moved to scratch memory; selecting among named
+// scalars keeps everything in VGPRs.
+struct R8 {
+  u32 x0, x1, x2, x3, x4, x5, x6, x7;
+  __device__ void put(int s, u32 v) {  // s is a compile-time constant after unrolling
+    switch (s) {
+      case 0: x0 = v; break;
+      case 1: x1 = v; break;
+      case 2: x2 = v; break;
+      case 3: x3 = v; break;
+      case 4: x4 = v; break;
+      case 5: x5 = v; break;
+      case 6: x6 = v; break;
+      default: x7 = v; break;
+    }
+  }
+  __device__ u32 get(u32 i) const {
+    // Bit masks rather than selects, so the choice stays arithmetic on
+    // registers instead of becoming an address computation.
+    return (x0 & (0u - (u32)(i == 0))) | (x1 & (0u - (u32)(i == 1))) |
+           (x2 & (0u - (u32)(i == 2))) | (x3 & (0u - (u32)(i == 3))) |
+           (x4 & (0u - (u32)(i == 4))) | (x5 & (0u - (u32)(i == 5))) |
+           (x6 & (0u - (u32)(i == 6))) | (x7 & (0u - (u32)(i == 7)));
+  }
+};
+static_assert(MAXS == 8, "R8 holds one value per source");
+
+__device__ inline u64 shfl_up_u64(u64 x, int d) {
+  u32 lo = __shfl_up((u32)x, d, 64);
+  u32 hi = __shfl_up((u32)(x >> 32), d, 64);
+  return ((u64)hi << 32) | lo;
+}
+
+__device__ inline u64 wave_incl_scan(u64 x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    u64 y = shfl_up_u64(x, d);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+__device__ inline u64 block_excl_scan(u64 x, u64* sh, u64* total) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  u64 inc = wave_incl_scan(x);
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  u64 off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < WG / 64; ++i) {
+    u64 s = sh[i];
+    if (i < w) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - x;
+}
+
+// View of the level buffers for one workgroup.
+struct Bufs {
+  u32* sm;
+  const DPlan* P;
+  const u32* rng0;  // [2*MAXN] in LDS
+  __device__ u32 lo(int b, u32 a, u32 i) const { return b < 0 ? rng0[2 * a] : sm[P->off_lo[b] + a * P->cap + i]; }
+  __device__ u32 hi(int b, u32 a, u32 i) const { return b < 0 ? rng0[2 * a + 1] : sm[P->off_hi[b] + a * P->cap + i]; }
+  __device__ u32 val(int b, u32 k, u32 i) const { return sm[P->off_val[b] + k * P->cap + i]; }
+};
+
+// Value of an operand while binding level L from parent item i of buffer L-1.
+__device__ inline u32 operand(const Bufs& B, const DOperand& o, int L, u32 i, u32 v) {
+  if (!o.is_var) return o.v;
+  if ((int)o.v == L) return v;
+  return B.val(L - 1, o.v, i);
+}
+
+// Candidate v for level L (from parent item i, or the root when L == 0):
+// the driver source `drv` supplies it at row r (its run of equal values ends
+// at dhi if known, else NONE); every other source of the level must contain
+// v inside its current range.  On success slo/shi hold each source's
+// narrowed range.
+__device__ inline bool try_candidate(const DPlan* P, const Bufs& B, int L, u32 i, u32 v, u32 drv,
+                                     u32 r, u32 dhi, R8& slo, R8& shi) {
+  const DLevel& lv = P->lvl[L];
+  for (u32 f = 0; f < lv.nne; ++f)
+    if (v == operand(B, lv.ne[f], L, i, v)) return false;
+  if (L == 0) {
+    // Level-0 values come straight from the root keys, so their bounds
+    // (constants only) are checked here; deeper levels clip candidate
+    // ranges to their bounds instead (prepare_item).
+    for (u32 b = 0; b < lv.nbnd; ++b) {
+      const u32 x = lv.bnd[b].o.v, adj = lv.bnd[b].adj;
+      if (!lv.bnd[b].is_hi) {
+        if (x > UMAX - adj || v < x + adj) return false;
+      } else {
+        if (x < adj || v > x - adj) return false;
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < MAXS; ++s) {
+    if (s < (int)lv.nsrc) {
+      const u32* col = lv.src[s].col;
+      const u32 a = lv.src[s].atom;
+      const bool last = lv.src[s].last != 0;
+      u32 lo = B.lo(L - 1, a, i), hi = B.hi(L - 1, a, i);
+      if ((u32)s == drv) {
+        // Only the first row of a run of equal values yields the candidate.
+        if (!last && r > lo && col[r - 1] == v) return false;
+        lo = r;
+        hi = last ? r + 1 : (dhi != NONE ? dhi : gallop_past(col, r + 1, hi, v));
+      } else {
+        u32 p = lower_bound_u32(col, lo, hi, v);
+        if (p >= hi || col[p] != v) return false;
+        lo = p;
+        hi = last ? p + 1 : gallop_past(col, p + 1, hi, v);
+      }
+      slo.put(s, lo);
+      shi.put(s, hi);
+    }
+  }
+  return true;
+}
+
+// Range of atom a after binding level L (narrowed if the atom is a source).
+__device__ inline void new_range(const DPlan* P, const Bufs& B, int L, u32 i, u32 a,
+                                 const R8& slo, const R8& shi, u32* lo, u32* hi) {
+  const u32 s = P->lvl[L].atom_src[a];
+  if (s != NONE) {
+    *lo = slo.get(s);
+    *hi = shi.get(s);
+  } else {
+    *lo = B.lo(L - 1, a, i);
+    *hi = B.hi(L - 1, a, i);
+  }
+}
+
+// After binding level L: every atom must still match something; choose the
+// level L+1 driver (smallest range) and clip its range to the value bounds of
+// level L+1.  Yields the candidate rows [clo, chi) of the new item.
+__device__ inline bool prepare_item(const DPlan* P, const Bufs& B, int L, u32 i, u32 v,
+                                    const R8& slo, const R8& shi, u32* drv,
+                                    u32* clo, u32* chi) {
+  for (u32 a = 0; a < P->natoms; ++a) {
+    u32 lo, hi;
+    new_range(P, B, L, i, a, slo, shi, &lo, &hi);
+    if (lo >= hi) return false;
+  }
+  const DLevel& nx = P->lvl[L + 1];
+  u32 best = 0, bsz = UMAX, blo = 0, bhi = 0;
+  for (u32 s = 0; s < nx.nsrc; ++s) {
+    u32 lo, hi;
+    new_range(P, B, L, i, nx.src[s].atom, slo, shi, &lo, &hi);
+    if (hi - lo < bsz) {
+      bsz = hi - lo;
+      best = s;
+      blo = lo;
+      bhi = hi;
+    }
+  }
+  u32 lov = 0, hiv = UMAX;
+  for (u32 b = 0; b < nx.nbnd; ++b) {
+    u32 x = operand(B, nx.bnd[b].o, L, i, v);
+    u32 adj = nx.bnd[b].adj;
+    if (!nx.bnd[b].is_hi) {
+      if (x > UMAX - adj) return false;
+      lov = max(lov, x + adj);
+    } else {
+      if (x < adj) return false;
+      hiv = min(hiv, x - adj);
+    }
+  }
+  if (lov > hiv) return false;
+  const u32* col = nx.src[best].col;
+  u32 lo = lov ? lower_bound_u32(col, blo, bhi, lov) : blo;
+  u32 hi = (hiv != UMAX) ? upper_bound_u32(col, lo, bhi, hiv) : bhi;
+  if (lo >= hi) return false;
+  *drv = best;
+  *clo = lo;
+  *chi = hi;
+  return true;
+}
+
+__device__ inline void store_item(const DPlan* P, const Bufs& B, int L, u32 i, u32 v, u32 pos,
+                                  const R8& slo, const R8& shi, u32 drv, u32 clo,
+                                  u32 chi) {
+  const u32 cap = P->cap;
+  u32* sm = B.sm;
+  for (int k = 0; k < L; ++k) sm[P->off_val[L] + k * cap + pos] = B.val(L - 1, k, i);
+  sm[P->off_val[L] + L * cap + pos] = v;
+  for (u32 a = 0; a < P->natoms; ++a) {
+    u32 lo, hi;
+    new_range(P, B, L, i, a, slo, shi, &lo, &hi);
+    sm[P->off_lo[L] + a * cap + pos] = lo;
+    sm[P->off_hi[L] + a * cap + pos] = hi;
+  }
+  sm[P->off_drv[L] + pos] = drv;
+  sm[P->off_clo[L] + pos] = clo;
+  sm[P->off_chi[L] + pos] = chi;
+}
+
+__device__ inline void emit_row(const DPlan* P, const Bufs& B, int L, u32 i, u32 v, u64 at) {
+  if (at >= P->out_rows) {  // never happens when count and materialize agree
+    atomicOr(P->err, 1u);
+    return;
+  }
+  for (u32 h = 0; h < P->head_arity; ++h) P->out[h][at] = operand(B, P->head[h], L, i, v);
+}
+
+struct WgState {
+  u32 n[MAXV];        // items in each level buffer
+  u64 total[MAXV];    // candidates of each level buffer
+  u64 cur[MAXV];      // candidates consumed
+  u64 out;            // rows counted / written so far
+  u64 key_next;       // next root key to turn into a level-0 item
+  u64 examined;       // candidates examined by this workgroup
+  u32 rng0[2 * MAXN];
+  u64 sh[WG / 64];
+};
+
+// Inclusive prefix of candidate counts of buffer b; sets total, resets cursor.
+__device__ void finalize_buffer(const DPlan* P, u32* sm, WgState& st, int b) {
+  const u32 n = st.n[b];
+  const u32 per = P->cap / WG;  // items per thread (1, 2 or 4)
+  u64* pre = reinterpret_cast<u64*>(sm + P->off_pre[b]);
+  u64 sum = 0;
+  for (u32 t = 0; t < per; ++t) {
+    u32 it = threadIdx.x * per + t;
+    sum += it < n ? (u64)(sm[P->off_chi[b] + it] - sm[P->off_clo[b] + it]) : 0;
+  }
+  u64 tot;
+  u64 run = block_excl_scan(sum, st.sh, &tot);
+  for (u32 t = 0; t < per; ++t) {
+    u32 it = threadIdx.x * per + t;
+    if (it < n) {
+      run += (u64)(sm[P->off_chi[b] + it] - sm[P->off_clo[b] + it]);
+      pre[it] = run;
+    }
+  }
+  if (threadIdx.x == 0) {
+    st.total[b] = tot;
+    st.cur[b] = 0;
+    st.examined += tot;
+  }
+  __syncthreads();
+}
+
+// Rank the lanes whose `alive` is set; returns the lane's rank, *tot the count.
+__device__ inline u64 rank_alive(bool alive, WgState& st, u64* tot) {
+  return block_excl_scan(alive ? 1 : 0, st.sh, tot);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSpace rs,
+                                             Partition part, u64* counts, const u64* offsets,
+                                             u64 wg0) {
+  extern __shared__ __align__(16) u32 sm[];
+  __shared__ WgState st;
+  const u64 b = wg0 + blockIdx.x;
+  const int m = (int)P->m;
+  u64 us, ue;
+  if (part.balance_off) {
+    us = b ? rs.C[b - 1] : 0;
+    ue = rs.C[b];
+  } else {
+    us = b * part.slice;
+    ue = us + part.slice < rs.T ? us + part.slice : rs.T;
+  }
+  if (threadIdx.x < 2 * MAXN) st.rng0[threadIdx.x] = rs.rng0[threadIdx.x];
+  if (us >= ue) {
+    if (MODE == 0 && threadIdx.x == 0) counts[b] = 0;
+    return;
+  }
+  const u64 kfirst = owner_key(rs.C, 0, rs.K, us);
+  const u64 klast = owner_key(rs.C, kfirst, rs.K, ue - 1);
+  if (threadIdx.x == 0) {
+    st.key_next = kfirst;
+    st.out = 0;
+    st.examined = 0;
+    for (int j = 0; j < MAXV; ++j) st.n[j] = 0, st.total[j] = 0, st.cur[j] = 0;
+  }
+  __syncthreads();
+  Bufs B{sm, P, st.rng0};
+  const u64 obase = MODE == 1 ? offsets[b] : 0;
+  u64 my_count = 0;  // leaf rows found by this lane (count mode)
+  int bl = -1;       // buffer being drained; -1 = root keys
+
+  for (;;) {
+    if (bl < 0) {
+      if (st.key_next > klast) break;
+      if (threadIdx.x == 0) st.n[0] = 0;
+      __syncthreads();
+      // Root keys -> level-0 items (or output rows when m == 1).
+      while (st.key_next <= klast && (m == 1 || st.n[0] + WG <= P->cap)) {
+        const u64 kk = st.key_next + threadIdx.x;
+        bool alive = kk <= klast;
+        u32 v = 0, drv = 0, clo = 0, chi = 0;
+        R8 slo{}, shi{};
+        if (alive) {
+          v = rs.U[kk];
+          alive = try_candidate(P, B, 0, 0, v, P->root_src, rs.S[kk], rs.S[kk + 1], slo, shi);
+        }
+        const u64 cs = (alive && kk) ? rs.C[kk - 1] : 0;
+        if (alive && m == 1) {
+          alive = cs >= us && cs < ue;  // its single unit lies in this slice
+        } else if (alive) {
+          alive = prepare_item(P, B, 0, 0, v, slo, shi, &drv, &clo, &chi);
+          if (alive) {
+            const u64 ce = rs.C[kk];
+            const u64 lo = cs > us ? cs : us, hi = ce < ue ? ce : ue;
+            alive = lo < hi;
+            const u32 c0 = clo;
+            clo = c0 + (u32)(lo - cs);
+            chi = c0 + (u32)(hi - cs);
+          }
+        }
+        if (m == 1) {
+          if (MODE == 0) {
+            my_count += alive ? 1 : 0;
+          } else {
+            u64 tot;
+            u64 rk = rank_alive(alive, st, &tot);
+            if (alive) emit_row(P, B, 0, 0, v, obase + st.out + rk);
+            __syncthreads();
+            if (threadIdx.x == 0) st.out += tot;
+          }
+        } else {
+          u64 tot;
+          u64 rk = rank_alive(alive, st, &tot);
+          if (alive) store_item(P, B, 0, 0, v, st.n[0] + (u32)rk, slo, shi, drv, clo, chi);
+          __syncthreads();
+          if (threadIdx.x == 0) st.n[0] += (u32)tot;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) st.key_next += WG;
+        __syncthreads();
+      }
+      if (m == 1) continue;
+      finalize_buffer(P, sm, st, 0);
+      bl = 0;
+      continue;
+    }
+
+    if (st.cur[bl] >= st.total[bl]) {  // buffer drained: go up
+      bl -= 1;
+      continue;
+    }
+    const int L = bl + 1;  // level whose variable the candidates bind
+    const u64* pre = reinterpret_cast<const u64*>(sm + P->off_pre[bl]);
+    const u32 nb = st.n[bl];
+
+    if (L == m - 1) {
+      // Leaf level: every surviving candidate is an output row.
+      if (MODE == 0 && P->leaf_fast) {
+        if (threadIdx.x == 0) my_count += st.total[bl] - st.cur[bl];
+        __syncthreads();
+        if (threadIdx.x == 0) st.cur[bl] = st.total[bl];
+        __syncthreads();
+        continue;
+      }
+      const u64 total = st.total[bl];
+      for (u64 g0 = st.cur[bl]; g0 < total; g0 += WG) {
+        const u64 g = g0 + threadIdx.x;
+        bool alive = g < total;
+        u32 i = 0, v = 0;
+        R8 slo{}, shi{};
+        if (alive) {
+          // Item owning candidate g: first i with pre[i] > g.
+          u32 lo = 0, hi = nb;
+          while (lo < hi) {
+            u32 mid = (lo + hi) >> 1;
+            if (pre[mid] <= g) lo = mid + 1; else hi = mid;
+          }
+          i = lo;
+          const u64 gb = i ? pre[i - 1] : 0;
+          const u32 r = sm[P->off_clo[bl] + i] + (u32)(g - gb);
+          const u32 drv = sm[P->off_drv[bl] + i];
+          v = P->lvl[L].src[drv].col[r];
+          alive = try_candidate(P, B, L, i, v, drv, r, NONE, slo, shi);
+        }
+        if (MODE == 0) {
+          my_count += alive ? 1 : 0;
+        } else {
+          u64 tot;
+          u64 rk = rank_alive(alive, st, &tot);
+          if (alive) emit_row(P, B, L, i, v, obase + st.out + rk);
+          __syncthreads();
+          if (threadIdx.x == 0) st.out += tot;
+          __syncthreads();
+        }
+      }
+      if (threadIdx.x == 0) st.cur[bl] = total;
+      __syncthreads();
+      continue;
+    }
+
+    // Inner level: expand candidates of buffer bl into buffer bl+1.
+    if (threadIdx.x == 0) st.n[L] = 0;
+    __syncthreads();
+    while (st.cur[bl] < st.total[bl] && st.n[L] + WG <= P->cap) {
+      const u64 total = st.total[bl];
+      const u64 g = st.cur[bl] + threadIdx.x;
+      bool alive = g < total;
+      u32 i = 0, v = 0, drv2 = 0, clo = 0, chi = 0;
+      R8 slo{}, shi{};
+      if (alive) {
+        u32 lo = 0, hi = nb;
+        while (lo < hi) {
+          u32 mid = (lo + hi) >> 1;
+          if (pre[mid] <= g) lo = mid + 1; else hi = mid;
+        }
+        i = lo;
+        const u64 gb = i ? pre[i - 1] : 0;
+        const u32 r = sm[P->off_clo[bl] + i] + (u32)(g - gb);
+        const u32 drv = sm[P->off_drv[bl] + i];
+        v = P->lvl[L].src[drv].col[r];
+        alive = try_candidate(P, B, L, i, v, drv, r, NONE, slo, shi) &&
+                prepare_item(P, B, L, i, v, slo, shi, &drv2, &clo, &chi);
+      }
+      u64 tot;
+      u64 rk = rank_alive(alive, st, &tot);
+      if (alive) store_item(P, B, L, i, v, st.n[L] + (u32)rk, slo, shi, drv2, clo, chi);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        st.n[L] += (u32)tot;
+        st.cur[bl] = (g - threadIdx.x) + WG < total ? (g - threadIdx.x) + WG : total;
+      }
+      __syncthreads();
+    }
+    finalize_buffer(P, sm, st, L);
+    bl = L;
+  }
+
+  if (MODE == 0) {
+    u64 tot;
+    block_excl_scan(my_count, st.sh, &tot);
+    if (threadIdx.x == 0) counts[b] = tot;
+  } else if (P->cand && threadIdx.x == 0) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(P->cand), (unsigned long long)st.examined);
+  }
+}
+
+// Per root key: the level-0 binding, its surviving work W (Alg. 1 Phase 1).
+__global__ __launch_bounds__(WG) void k_hist(const DPlan* __restrict__ P, RootSpace rs, u64* W,
+                                             u32* klo, u32* kd, u32 xprod) {
+  __shared__ u32 rng0[2 * MAXN];
+  if (threadIdx.x < 2 * MAXN) rng0[threadIdx.x] = rs.rng0[threadIdx.x];
+  __syncthreads();
+  const u64 kk = (u64)blockIdx.x * WG + threadIdx.x;
+  if (kk >= rs.K) return;
+  Bufs B{nullptr, P, rng0};
+  R8 slo{}, shi{};
+  const u32 v = rs.U[kk];
+  bool alive = try_candidate(P, B, 0, 0, v, P->root_src, rs.S[kk], rs.S[kk + 1], slo, shi);
+  u64 w = 0;
+  if (alive) {
+    if (P->m == 1) {
+      w = 1;
+    } else if (xprod) {
+      // Cross product of independent single-source levels: W = prod d_j.
+      w = 1;
+      for (u32 a = 0; a < P->natoms && w; ++a) {
+        u32 lo, hi;
+        new_range(P, B, 0, 0, a, slo, shi, &lo, &hi);
+        if (lo >= hi) w = 0;
+      }
+      for (u32 j = 1; j < P->m && w; ++j) {
+        u32 lo, hi;
+        new_range(P, B, 0, 0, P->lvl[j].src[0].atom, slo, shi, &lo, &hi);
+        klo[(u64)j * rs.K + kk] = lo;
+        kd[(u64)j * rs.K + kk] = hi - lo;
+        w *= (u64)(hi - lo);
+      }
+    } else {
+      u32 drv, clo, chi;
+      if (prepare_item(P, B, 0, 0, v, slo, shi, &drv, &clo, &chi)) w = chi - clo;
+    }
+  }
+  W[kk] = w;
+}
+
+// Each unit of a cross-product plan is one output row (the work-unit decode
+// of Sec. 5): local = g - C[key-1], then mixed-radix digits over the levels.
+__global__ __launch_bounds__(WG) void k_xprod(const DPlan* __restrict__ P, RootSpace rs,
+                                              const u32* klo, const u32* kd) {
+  __shared__ u64 kr[2];
+  const u64 ub = (u64)blockIdx.x * WG;
+  const u64 ue = ub + WG < rs.T ? ub + WG : rs.T;
+  if (threadIdx.x == 0) {
+    u64 k0 = owner_key(rs.C, 0, rs.K, ub);
+    kr[0] = k0;
+    kr[1] = owner_key(rs.C, k0, rs.K, ue - 1) + 1;
+  }
+  __syncthreads();
+  const u64 g = ub + threadIdx.x;
+  if (g >= rs.T) return;
+  if (g >= P->out_rows) {
+    atomicOr(P->err, 1u);
+    return;
+  }
+  const u64 kk = owner_key(rs.C, kr[0], kr[1], g);
+  u64 local = g - (kk ? rs.C[kk - 1] : 0);
+  u32 vals[MAXV];
+  vals[0] = rs.U[kk];
+  for (int j = (int)P->m - 1; j >= 1; --j) {
+    const u32 d = kd[(u64)j * rs.K + kk];
+    u32 ij;
+    if (local <= 0xffffffffull) {
+      u32 l32 = (u32)local;
+      ij = l32 % d;
+      local = l32 / d;
+    } else {
+      ij = (u32)(local % d);
+      local /= d;
+    }
+    const u32 x = P->lvl[j].src[0].col[klo[(u64)j * rs.K + kk] + ij];
+#pragma unroll
+    for (int t = 1; t < MAXV; ++t)
+      if (t == j) vals[t] = x;
+  }
+  for (u32 h = 0; h < P->head_arity; ++h) {
+    const DOperand& o = P->head[h];
+    u32 x = o.v;
+    if (o.is_var) {
+#pragma unroll
+      for (int t = 0; t < MAXV; ++t)
+        if ((u32)t == o.v) x = vals[t];
+    }
+    P->out[h][g] = x;
+  }
+}
+
+// Narrow every atom by its leading constant columns.
+__global__ void k_init_ranges(const DPlan* __restrict__ P, u32* rng0) {
+  const u32 a = threadIdx.x;
+  if (a >= MAXN) return;
+  if (a >= P->natoms) {
+    rng0[2 * a] = 0;
+    rng0[2 * a + 1] = 0;
+    return;
+  }
+  u32 lo = 0, hi = P->atom_n[a];
+  for (u32 c = 0; c < P->atom_nconst[a]; ++c) {
+    const u32* col = P->atom_col[a][c];
+    const u32 x = P->atom_const[a][c];
+    u32 l2 = lower_bound_u32(col, lo, hi, x);
+    hi = upper_bound_u32(col, l2, hi, x);
+    lo = l2;
+  }
+  rng0[2 * a] = lo;
+  rng0[2 * a + 1] = hi;
+}
+
+// Root keys: first rows of runs of equal values in [lo, hi) of `col`.
+__global__ __launch_bounds__(WG) void k_key_flags(const u32* col, const u32* rng0, u32 atom, u32 n,
+                                                  u32* flags) {
+  const u64 r = (u64)blockIdx.x * WG + threadIdx.x;
+  if (r >= n) return;
+  const u32 lo = rng0[2 * atom], hi = rng0[2 * atom + 1];
+  flags[r] = (r >= lo && r < hi && (r == lo || col[r] != col[r - 1])) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(WG) void k_key_compact(const u32* col, const u32* flags,
+                                                    const u64* pos, u32 n, u32* U, u32* S) {
+  const u64 r = (u64)blockIdx.x * WG + threadIdx.x;
+  if (r >= n || !flags[r]) return;
+  U[pos[r]] = col[r];
+  S[pos[r]] = (u32)r;
+}
+
+__global__ void k_key_end(const u32* rng0, u32 atom, u64 K, u32* S) { S[K] = rng0[2 * atom + 1]; }
+
+u32 grid1(u64 n) {
+  u64 g = ceil_div(n, WG);
+  if (g > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "grid too large");
+  return (u32)(g ? g : 1);
+}
+
+}  // namespace
+
+void join_init_ranges(Ctx c, const DPlan* d_plan, u32 natoms, u32* d_rng0) {
+  (void)natoms;
+  k_init_ranges<<<1, 64, 0, c.s>>>(d_plan, d_rng0);
+  WCDL_HIP(hipGetLastError());
+}
+
+void join_root_flags(Ctx c, const u32* col, const u32* d_rng0, u32 atom, u32 n_rows, u32* flags,
+                     u64* pos, u64* d_K) {
+  if (n_rows == 0) {
+    fill_u64(c, d_K, 1, 0);
+    return;
+  }
+  k_key_flags<<<grid1(n_rows), WG, 0, c.s>>>(col, d_rng0, atom, n_rows, flags);
+  WCDL_HIP(hipGetLastError());
+  scan_u32_excl(c, flags, pos, n_rows, d_K);
+}
+
+void join_root_compact(Ctx c, const u32* col, const u32* d_rng0, u32 atom, u32 n_rows,
+                       const u32* flags, const u64* pos, u64 K, u32* U, u32* S) {
+  if (n_rows) {
+    k_key_compact<<<grid1(n_rows), WG, 0, c.s>>>(col, flags, pos, n_rows, U, S);
+    WCDL_HIP(hipGetLastError());
+  }
+  k_key_end<<<1, 1, 0, c.s>>>(d_rng0, atom, K, S);
+  WCDL_HIP(hipGetLastError());
+}
+
+void join_histogram(Ctx c, const DPlan* d_plan, const RootSpace& rs, u64* W, u32* klo, u32* kd,
+                    u32 m) {
+  (void)m;
+  if (rs.K == 0) return;
+  k_hist<<<grid1(rs.K), WG, 0, c.s>>>(d_plan, rs, W, klo, kd, klo != nullptr);
+  WCDL_HIP(hipGetLastError());
+}
+
+void join_run(Ctx c, const DPlan* d_plan, const RootSpace& rs, const Partition& part,
+              u32 lds_bytes, int mode, u64* counts, const u64* offsets, u64 wg0, u64 nwg) {
+  if (nwg == 0) return;
+  if (nwg > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "too many workgroups");
+  if (lds_bytes > 60 * 1024) {
+    // Deep plans: allow more than the default dynamic LDS (gfx950 has 160 KB per CU).
+    WCDL_HIP(hipFuncSetAttribute((const void*)k_join<0>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+    WCDL_HIP(hipFuncSetAttribute((const void*)k_join<1>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+  }
+  if (mode == 0)
+    k_join<0><<<(u32)nwg, WG, lds_bytes, c.s>>>(d_plan, rs, part, counts, offsets, wg0);
+  else
+    k_join<1><<<(u32)nwg, WG, lds_bytes, c.s>>>(d_plan, rs, part, counts, offsets, wg0);
+  WCDL_HIP(hipGetLastError());
+}
+
+void join_xprod(Ctx c, const DPlan* d_plan, const RootSpace& rs, const u32* klo, const u32* kd,
+                u32 m) {
+  (void)m;
+  if (rs.T == 0) return;
+  k_xprod<<<grid1(rs.T), WG, 0, c.s>>>(d_plan, rs, klo, kd);
+  WCDL_HIP(hipGetLastError());
+}
+
+}  // namespace wcdl

@@ -1,0 +1,303 @@
+"""Python binding of the C ABI in include/wcdl.h (argument marshalling only).
+
+Every step of evaluation runs in the HIP kernels of ``libwcdl.so``.  PyTorch
+supplies device memory (through its caching allocator, passed to the engine as
+an allocator callback) and streams.  If the library has not been built, every
+entry point raises: there is no fallback path.
+
+    from paper_2604_20073_amd import Engine
+    e = Engine()
+    e.declare("edge", 2); e.declare("path", 2)
+    e.add_rules("path(x,y) :- edge(x,y). path(x,z) :- path(x,y), edge(y,z).")
+    e.load("edge", edges)            # (n, 2) uint32: numpy or torch (CPU or GPU)
+    stats = e.run()
+    path = e.read_numpy("path")      # (|path|, 2) uint32, sorted, unique
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwcdl.so")
+
+WCDL_F_BALANCE_OFF = 0x1
+WCDL_F_STREAMS_OFF = 0x2
+WCDL_F_XPROD_OFF = 0x4
+PHASES = ["histogram", "count", "materialize", "delta", "index", "merge", "load", "other"]
+KERNELS = ["join_count", "join_materialize", "join_histogram", "unused"]
+ERRORS = {-1: "E_INVALID", -2: "E_ARITY", -3: "E_UNKNOWN_REL", -4: "E_UNSAFE_RULE",
+          -5: "E_UNSUPPORTED", -6: "E_STATE", -7: "E_NOMEM", -8: "E_BUDGET", -9: "E_DEVICE",
+          -10: "E_PARSE"}
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("n_streams", ctypes.c_uint32),
+                ("streams", ctypes.POINTER(ctypes.c_void_p)), ("alloc", _Allocator),
+                ("mem_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("wg_per_cu", ctypes.c_uint32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint64), ("derived_rows", ctypes.c_uint64),
+                ("candidate_rows", ctypes.c_uint64), ("join_units", ctypes.c_uint64),
+                ("wall_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 8),
+                ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_uint64 * 4),
+                ("candidates_checked", ctypes.c_uint64)]
+
+
+class WcdlError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+EXPORTS = [
+    "wcdl_config_default", "wcdl_create", "wcdl_destroy", "wcdl_last_error",
+    "wcdl_declare_relation", "wcdl_relation_id", "wcdl_load_columns", "wcdl_clear_relation",
+    "wcdl_add_rule", "wcdl_add_rules_text", "wcdl_rule_count", "wcdl_split_rule", "wcdl_run",
+    "wcdl_relation_size", "wcdl_read_columns", "wcdl_delta_sizes", "wcdl_work_slice",
+    "wcdl_owner_key", "wcdl_decode_unit",
+]
+
+
+def lib():
+    """Load libwcdl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2604_20073_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+    pu32, pu64 = ctypes.POINTER(u32), ctypes.POINTER(u64)
+    L.wcdl_config_default.argtypes = [ctypes.POINTER(_Config)]
+    L.wcdl_create.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(P)]
+    L.wcdl_destroy.argtypes = [P]
+    L.wcdl_last_error.argtypes = [P]
+    L.wcdl_last_error.restype = ctypes.c_char_p
+    L.wcdl_declare_relation.argtypes = [P, ctypes.c_char_p, u32, pu32]
+    L.wcdl_relation_id.argtypes = [P, ctypes.c_char_p, pu32]
+    L.wcdl_load_columns.argtypes = [P, u32, ctypes.POINTER(P), u64, ctypes.c_int]
+    L.wcdl_clear_relation.argtypes = [P, u32]
+    L.wcdl_add_rules_text.argtypes = [P, ctypes.c_char_p]
+    L.wcdl_rule_count.argtypes = [P, pu32]
+    L.wcdl_split_rule.argtypes = [P, u32, pu32, u32, pu32]
+    L.wcdl_run.argtypes = [P, ctypes.POINTER(_Stats)]
+    L.wcdl_relation_size.argtypes = [P, u32, pu64]
+    L.wcdl_read_columns.argtypes = [P, u32, ctypes.POINTER(P), u64, pu64, ctypes.c_int]
+    L.wcdl_delta_sizes.argtypes = [P, u32, pu64, u64, pu64]
+    L.wcdl_work_slice.argtypes = [u64, u64, u64, pu64, pu64]
+    L.wcdl_work_slice.restype = None
+    L.wcdl_owner_key.argtypes = [pu64, u64, u64]
+    L.wcdl_owner_key.restype = u64
+    L.wcdl_decode_unit.argtypes = [pu64, u64, pu32, u64, pu64, pu64, pu64]
+    L.wcdl_decode_unit.restype = None
+    _lib = L
+    return L
+
+
+# ---- host-side views of the work partition (no GPU needed) -----------------
+
+def work_slice(T: int, p: int, b: int):
+    s, e = ctypes.c_uint64(), ctypes.c_uint64()
+    lib().wcdl_work_slice(T, p, b, ctypes.byref(s), ctypes.byref(e))
+    return s.value, e.value
+
+
+def owner_key(C, g: int) -> int:
+    c = np.ascontiguousarray(C, dtype=np.uint64)
+    return int(lib().wcdl_owner_key(c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), len(c), g))
+
+
+def decode_unit(C, d2, g: int):
+    c = np.ascontiguousarray(C, dtype=np.uint64)
+    d = np.ascontiguousarray(d2, dtype=np.uint32)
+    k, i1, i2 = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    lib().wcdl_decode_unit(c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), len(c),
+                           d.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), g,
+                           ctypes.byref(k), ctypes.byref(i1), ctypes.byref(i2))
+    return k.value, i1.value, i2.value
+
+
+class Engine:
+    """One engine (one program over one set of relations) on one GPU."""
+
+    def __init__(self, device: int = 0, streams=None, flags: int = 0, mem_budget: int = 0,
+                 wg_per_cu: int = 0, torch_alloc: bool = True):
+        import torch  # device memory and streams come from PyTorch
+
+        self._torch = torch
+        self._lib = lib()
+        self._e = ctypes.c_void_p()
+        self.device = device
+        cfg = _Config()
+        self._lib.wcdl_config_default(ctypes.byref(cfg))
+        cfg.device = device
+        cfg.flags = flags
+        cfg.mem_budget_bytes = mem_budget
+        cfg.wg_per_cu = wg_per_cu
+        self._keep = []
+        if torch_alloc:
+            dev = torch.device("cuda", device)
+
+            def _alloc(ctx, nbytes, stream):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream or 0)
+                except Exception:
+                    return None
+
+            def _free(ctx, ptr, nbytes, stream):
+                try:
+                    torch.cuda.caching_allocator_delete(ptr)
+                except Exception:
+                    pass
+
+            a, f = _ALLOC_FN(_alloc), _FREE_FN(_free)
+            self._keep += [a, f]
+            cfg.alloc = _Allocator(a, f, None)
+        if streams:
+            arr = (ctypes.c_void_p * len(streams))(*[ctypes.c_void_p(s.cuda_stream) for s in streams])
+            self._keep.append(arr)
+            self._streams = list(streams)
+            cfg.n_streams = len(streams)
+            cfg.streams = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+        rc = self._lib.wcdl_create(ctypes.byref(cfg), ctypes.byref(self._e))
+        if rc != 0:
+            raise WcdlError(rc, "wcdl_create failed")
+        self.arity = {}
+        self.ids = {}
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_e", None) and self._e.value:
+            self._lib.wcdl_destroy(self._e)
+            self._e = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc):
+        if rc != 0:
+            raise WcdlError(rc, self._lib.wcdl_last_error(self._e).decode())
+
+    # -- program -----------------------------------------------------------
+    def declare(self, name: str, arity: int) -> int:
+        rid = ctypes.c_uint32()
+        self._check(self._lib.wcdl_declare_relation(self._e, name.encode(), arity, ctypes.byref(rid)))
+        self.arity[name] = arity
+        self.ids[name] = rid.value
+        return rid.value
+
+    def add_rules(self, text: str):
+        self._check(self._lib.wcdl_add_rules_text(self._e, text.encode()))
+
+    def rule_count(self) -> int:
+        n = ctypes.c_uint32()
+        self._check(self._lib.wcdl_rule_count(self._e, ctypes.byref(n)))
+        return n.value
+
+    def split_rule(self, rule_id: int, atoms) -> int:
+        a = (ctypes.c_uint32 * len(atoms))(*atoms)
+        h = ctypes.c_uint32()
+        self._check(self._lib.wcdl_split_rule(self._e, rule_id, a, len(atoms), ctypes.byref(h)))
+        return h.value
+
+    # -- data --------------------------------------------------------------
+    def load(self, name: str, rows):
+        """Add facts: rows is an (n, arity) array of uint32 values (numpy,
+        or a torch tensor of 32-bit integers on the CPU or the GPU)."""
+        torch = self._torch
+        k = self.arity[name]
+        if isinstance(rows, torch.Tensor):
+            t = rows.reshape(-1, k)
+            if t.dtype not in (torch.int32, torch.uint32):
+                raise TypeError("rows must hold 32-bit integers")
+            cols = [t[:, j].contiguous() for j in range(k)]
+            on_dev = 1 if t.is_cuda else 0
+            ptrs = [c.data_ptr() for c in cols]
+            n = t.shape[0]
+            keep = cols
+        else:
+            a = np.asarray(rows)
+            if a.dtype != np.uint32:
+                if a.size and (a.min() < 0 or a.max() > 0xFFFFFFFF):
+                    raise ValueError("values must fit in uint32")
+                a = a.astype(np.uint32)
+            a = a.reshape(-1, k)
+            cols = [np.ascontiguousarray(a[:, j]) for j in range(k)]
+            ptrs = [c.ctypes.data for c in cols]
+            n = a.shape[0]
+            on_dev = 0
+            keep = cols
+        arr = (ctypes.c_void_p * k)(*ptrs)
+        self._check(self._lib.wcdl_load_columns(self._e, self.ids[name], arr, n, on_dev))
+        del keep
+
+    def clear(self, name: str):
+        self._check(self._lib.wcdl_clear_relation(self._e, self.ids[name]))
+
+    # -- evaluation ----------------------------------------------------------
+    def run(self) -> dict:
+        s = _Stats()
+        self._check(self._lib.wcdl_run(self._e, ctypes.byref(s)))
+        return {"rounds": s.rounds, "derived_rows": s.derived_rows,
+                "candidate_rows": s.candidate_rows, "join_units": s.join_units,
+                "wall_ms": s.wall_ms, "phase_ms": dict(zip(PHASES, list(s.phase_ms))),
+                "kernel_ms": dict(zip(KERNELS, list(s.kernel_ms))),
+                "kernel_launches": dict(zip(KERNELS, [int(x) for x in s.kernel_launches])),
+                "candidates_checked": s.candidates_checked}
+
+    def size(self, name: str) -> int:
+        n = ctypes.c_uint64()
+        self._check(self._lib.wcdl_relation_size(self._e, self.ids[name], ctypes.byref(n)))
+        return n.value
+
+    def read(self, name: str):
+        """Relation as a (n, arity) int32 torch tensor on the GPU (bit pattern
+        of the uint32 values), sorted and unique."""
+        torch = self._torch
+        k, n = self.arity[name], self.size(name)
+        out = torch.empty((k, max(n, 1)), dtype=torch.int32, device=f"cuda:{self.device}")
+        arr = (ctypes.c_void_p * k)(*[out[j].data_ptr() for j in range(k)])
+        w = ctypes.c_uint64()
+        self._check(self._lib.wcdl_read_columns(self._e, self.ids[name], arr, n, ctypes.byref(w), 1))
+        return out[:, :n].t()
+
+    def read_numpy(self, name: str) -> np.ndarray:
+        """Relation as a (n, arity) uint32 numpy array, sorted and unique."""
+        k, n = self.arity[name], self.size(name)
+        out = np.empty((k, max(n, 1)), dtype=np.uint32)
+        arr = (ctypes.c_void_p * k)(*[out[j].ctypes.data for j in range(k)])
+        w = ctypes.c_uint64()
+        self._check(self._lib.wcdl_read_columns(self._e, self.ids[name], arr, n, ctypes.byref(w), 0))
+        return np.ascontiguousarray(out[:, :n].T)
+
+    def delta_sizes(self, name: str) -> list:
+        cnt = ctypes.c_uint64()
+        self._check(self._lib.wcdl_delta_sizes(self._e, self.ids[name], None, 0, ctypes.byref(cnt)))
+        buf = (ctypes.c_uint64 * max(cnt.value, 1))()
+        self._check(self._lib.wcdl_delta_sizes(self._e, self.ids[name], buf, cnt.value,
+                                               ctypes.byref(cnt)))
+        return [int(buf[i]) for i in range(cnt.value)]

@@ -1,0 +1,241 @@
+"""Parity of the HIP engine with the CPU oracle (GPU required).
+
+Results must be bit-exact: the same sorted, deduplicated relations, and the
+same per-round delta sizes of every recursive stratum.  Inputs are seeded
+synthetic relations shaped like the paper's workloads at sizes the oracle
+finishes in seconds, spanning many workgroup slices and ragged tails.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_20073_amd import (WCDL_F_BALANCE_OFF, WCDL_F_STREAMS_OFF, WCDL_F_XPROD_OFF,
+                                  Engine, WcdlError)
+from paper_2604_20073_amd import workloads as W
+from tests.checkers import render
+from tests.test_oracle_pins import ANDERSEN, ARITY, C4, PROGRAMS, Q4, TC, TRI
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_eval(relations, rules, facts, **kw):
+    e = Engine(**kw)
+    for n, k in relations.items():
+        e.declare(n, k)
+    e.add_rules(rules)
+    for n, rows in facts.items():
+        e.load(n, rows)
+    stats = e.run()
+    return e, {n: e.read_numpy(n) for n in relations}, stats
+
+
+def check_parity(relations, rules, facts, deltas=True, **kw):
+    o, expect = oracle.evaluate(relations, rules, facts)
+    e, got, stats = gpu_eval(relations, rules, facts, **kw)
+    for n in relations:
+        assert got[n].shape == expect[n].shape, (n, got[n].shape, expect[n].shape)
+        assert np.array_equal(got[n], expect[n]), n
+        if deltas:
+            assert e.delta_sizes(n) == o.delta_sizes(n), n
+    if deltas:
+        assert stats["rounds"] == o.rounds
+    e.close()
+    return got, stats
+
+
+# --------------------------------------------------------------------------
+# The plain-engine workload: ER 1,000 nodes / 5,000 edges; TC and triangles.
+# --------------------------------------------------------------------------
+
+def test_config0_tc_and_triangles():
+    edges = W.er_graph(1000, 5000, W.SEED_BASE + 0)
+    got, stats = check_parity({"edge": 2, "path": 2, "tri": 3}, TC + "\n" + TRI, {"edge": edges})
+    assert len(got["path"]) > 900_000 and len(got["tri"]) > 0
+    assert stats["derived_rows"] == len(got["path"]) + len(got["tri"])
+
+
+@pytest.mark.parametrize("n", [2, 3, 17, 300])
+def test_tc_path_closed_form(n):
+    got, stats = check_parity({"edge": 2, "path": 2}, TC, {"edge": W.path_graph(n)})
+    assert len(got["path"]) == n * (n - 1) // 2
+
+
+@pytest.mark.parametrize("n", [1, 5, 64])
+def test_tc_cycle_closed_form(n):
+    edges = W.cycle_graph(n) if n > 1 else np.array([[0, 0]], dtype=np.uint32)
+    got, _ = check_parity({"edge": 2, "path": 2}, TC, {"edge": edges})
+    assert len(got["path"]) == n * n
+
+
+@pytest.mark.parametrize("n", [3, 9, 40])
+def test_complete_graph_counts(n):
+    rels = {"edge": 2, "path": 2, "tri": 3, "q": 4}
+    got, _ = check_parity(rels, TC + "\n" + TRI + "\n" + Q4, {"edge": W.complete_graph(n)})
+    assert len(got["path"]) == n * n
+    assert len(got["tri"]) == n * (n - 1) * (n - 2)
+
+
+# --------------------------------------------------------------------------
+# Rule shapes: non-linear recursion, mutual recursion, constants, repeated
+# variables, comparisons, several strata.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", sorted(PROGRAMS))
+@pytest.mark.parametrize("seed", range(2))
+def test_program_shapes(name, seed):
+    rules = PROGRAMS[name]
+    names = sorted({r.head[0] for r in rules} | {a[0] for r in rules for a in r.body})
+    edges = W.er_graph(40, 110, 600 + seed)
+    check_parity({n: ARITY[n] for n in names}, render(rules), {"edge": edges})
+
+
+def test_repeated_variables_and_constants():
+    rules = """self(x) :- edge(x, x).
+loop2(x, y) :- edge(x, y), edge(y, x).
+from0(y) :- edge(0, y).
+two(x, z) :- edge(x, y), edge(y, z), x != z, y > 3.
+diag(x, x) :- edge(x, y), y <= 10.
+"""
+    edges = np.concatenate([W.er_graph(30, 200, 5), np.array([[3, 3], [7, 7], [0, 9]], np.uint32)])
+    check_parity({"edge": 2, "self": 1, "loop2": 2, "from0": 1, "two": 2, "diag": 2}, rules,
+                 {"edge": edges}, deltas=False)
+
+
+def test_four_cycles_and_cliques_rmat():
+    edges = W.rmat_graph(11, 12000, 77)
+    check_parity({"e": 2, "c": 4}, C4, {"e": edges}, deltas=False)
+    check_parity({"edge": 2, "tri": 3, "q": 4}, TRI + "\n" + Q4, {"edge": edges}, deltas=False)
+
+
+def test_andersen_small():
+    rel = W.andersen_scaled(W.SEED_BASE + 2, 0.004)
+    names = {"addressOf": 2, "assign": 2, "load": 2, "store": 2, "pt": 2}
+    got, stats = check_parity(names, ANDERSEN, rel)
+    assert len(got["pt"]) > 0 and stats["rounds"] > 3
+
+
+# --------------------------------------------------------------------------
+# Schedules and rewrites give identical results (monotone evaluation).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("flags", [WCDL_F_BALANCE_OFF, WCDL_F_STREAMS_OFF, WCDL_F_XPROD_OFF,
+                                   WCDL_F_BALANCE_OFF | WCDL_F_STREAMS_OFF | WCDL_F_XPROD_OFF])
+def test_flags_do_not_change_results(flags):
+    edges = W.rmat_graph(10, 6000, 31)
+    rels = {"edge": 2, "path": 2, "tri": 3}
+    check_parity(rels, TC + "\n" + TRI, {"edge": edges}, flags=flags)
+
+
+@pytest.mark.parametrize("wg_per_cu", [1, 3, 64])
+def test_partition_granularity(wg_per_cu):
+    edges = W.rmat_graph(12, 30000, 32)
+    check_parity({"edge": 2, "tri": 3, "q": 4}, TRI + "\n" + Q4, {"edge": edges}, deltas=False,
+                 wg_per_cu=wg_per_cu)
+
+
+def test_helper_split_keeps_results():
+    rel = W.andersen_scaled(W.SEED_BASE + 2, 0.003)
+    names = {"addressOf": 2, "assign": 2, "load": 2, "store": 2, "pt": 2}
+    o, expect = oracle.evaluate(names, ANDERSEN, rel)
+    e = Engine()
+    for n, k in names.items():
+        e.declare(n, k)
+    e.add_rules(ANDERSEN)
+    # Rule 2: pt(v,h) :- load(v,p), pt(p,q), pt(q,h): factor load(v,p), pt(p,q).
+    e.declare_helper = e.split_rule(2, [0, 1])
+    for n, rows in rel.items():
+        e.load(n, rows)
+    e.run()
+    assert np.array_equal(e.read_numpy("pt"), expect["pt"])
+    e.close()
+
+
+def test_deterministic_across_runs():
+    edges = W.rmat_graph(11, 15000, 9)
+    e = Engine()
+    e.declare("edge", 2)
+    e.declare("path", 2)
+    e.add_rules(TC)
+    e.load("edge", edges)
+    e.run()
+    a = e.read_numpy("path")
+    d1 = e.delta_sizes("path")
+    e.run()
+    assert np.array_equal(a, e.read_numpy("path"))
+    assert d1 == e.delta_sizes("path")
+    e.close()
+
+
+# --------------------------------------------------------------------------
+# Edge cases
+# --------------------------------------------------------------------------
+
+def test_empty_and_single_inputs():
+    rels = {"edge": 2, "path": 2, "tri": 3}
+    check_parity(rels, TC + "\n" + TRI, {"edge": np.zeros((0, 2), np.uint32)})
+    check_parity(rels, TC + "\n" + TRI, {"edge": np.array([[5, 6]], np.uint32)})
+
+
+def test_extreme_values():
+    big = 0xFFFFFFFF
+    edges = np.array([[big, 0], [0, big], [big - 1, big], [big, big - 1], [1, 2], [2, big]],
+                     dtype=np.uint32)
+    rules = TC + "\n" + TRI + "\nlt(x, y) :- edge(x, y), x < y.\n"
+    check_parity({"edge": 2, "path": 2, "tri": 3, "lt": 2}, rules, {"edge": edges}, deltas=False)
+
+
+def test_duplicate_loads_are_sets():
+    edges = W.er_graph(50, 200, 4)
+    e = Engine()
+    e.declare("edge", 2)
+    e.load("edge", edges)
+    e.load("edge", edges[::-1])
+    e.load("edge", np.concatenate([edges, edges]))
+    got = e.read_numpy("edge")
+    assert np.array_equal(got, np.unique(edges, axis=0))
+    e.close()
+
+
+def test_device_input_and_output():
+    import torch
+    edges = W.er_graph(200, 900, 12)
+    e = Engine()
+    e.declare("edge", 2)
+    e.declare("path", 2)
+    e.add_rules(TC)
+    e.load("edge", torch.from_numpy(edges.astype(np.int32)).cuda())
+    e.run()
+    dev = e.read("path")
+    assert dev.is_cuda
+    _, expect = oracle.evaluate({"edge": 2, "path": 2}, TC, {"edge": edges})
+    assert np.array_equal(dev.cpu().numpy().astype(np.uint32), expect["path"])
+    e.close()
+
+
+def test_errors_do_not_poison_the_engine():
+    e = Engine()
+    e.declare("edge", 2)
+    e.declare("p", 2)
+    with pytest.raises(WcdlError):
+        e.add_rules("p(x, z) :- edge(x, y).")
+    with pytest.raises(WcdlError):
+        e.add_rules("p(x) :- edge(x, y).")
+    e.add_rules("p(x, y) :- edge(y, x).")
+    e.load("edge", np.array([[1, 2]], np.uint32))
+    e.run()
+    assert e.read_numpy("p").tolist() == [[2, 1]]
+    e.close()
+
+
+def test_memory_budget_is_enforced():
+    edges = W.complete_graph(60)
+    e = Engine(mem_budget=1 << 16)
+    e.declare("edge", 2)
+    e.declare("tri", 3)
+    e.add_rules(TRI)
+    e.load("edge", edges)
+    with pytest.raises(WcdlError) as ei:
+        e.run()
+    assert ei.value.code == -8
+    e.close()
