@@ -174,6 +174,8 @@ def main():
         "cpu_baseline": base,
         "phase_ms": phases,
         "kernel_ms": kernels,
+        "candidates_per_level": [x // args.steps for x in
+                                 np.sum([s["candidates_per_level"] for s in stats], axis=0).tolist()],
     }
     print(json.dumps(out), flush=True)
     e.close()

@@ -95,7 +95,7 @@ typedef struct {
                                 with WCDL_E_BUDGET */
   uint32_t flags;            /* WCDL_F_* */
   uint32_t wg_per_cu;        /* work-partition oversubscription: p = 256 CUs x
-                                wg_per_cu workgroups per join; 0 = default (8) */
+                                wg_per_cu workgroups per join; 0 = default (32) */
 } wcdl_config;
 
 /* Fill `cfg` with defaults (device 0, own streams, hipMalloc, no budget). */
@@ -235,6 +235,8 @@ typedef struct {
   uint64_t candidates_checked; /* candidate values tested by materialize
                                   kernels (one per element of the smallest
                                   list of every intersection) */
+  uint64_t candidates_per_level[WCDL_MAX_VARS]; /* the same, by join level
+                                  (level 0 = root keys), summed over rules */
 } wcdl_run_stats;
 
 /* Evaluate every stratum to its fixpoint (Sec. 2 stratification; the loop of

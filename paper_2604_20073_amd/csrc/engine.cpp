@@ -382,6 +382,7 @@ struct Version {
   std::vector<u32> level_var;   // variable id at each level
   std::vector<AtomUse> atoms;
   std::vector<std::vector<u32>> src_pos;  // per level, per source: column position in its atom
+  std::vector<std::vector<bool>> want_dir;  // per level, per source: unnarrowed first column
   DPlan plan{};                 // pointers filled at evaluation time
   bool sorted_output = false;   // rows come out sorted by head columns, unique
   u32 lds_bytes = 0;
@@ -512,7 +513,7 @@ std::vector<u32> choose_order(const Rule& r, int delta_atom) {
   return order;
 }
 
-constexpr u32 LDS_BUDGET = 60 * 1024;
+constexpr u32 LDS_BUDGET = 48 * 1024;
 
 // Build a version of rule `ri` with atom `delta_atom` read from the delta (or
 // -1 for none).  Pointers are filled later.
@@ -614,12 +615,80 @@ Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
     b.adj = (c.op == OP_LT) ? 1u : 0u;
     b.is_hi = a_is_level ? 1u : 0u;  // x_L < other -> upper bound; other < x_L -> lower
   }
+  // Range slots and aliases.  The range of an atom after binding levels
+  // 0..b depends only on its sorted copy, its constants and the variables
+  // bound in its leading columns; atoms agreeing on all three share a slot.
+  auto range_key = [&](size_t ai, int b) {
+    const AtomUse& u = v.atoms[ai];
+    std::vector<u64> key{u.rel, u.delta ? 1ull : 0ull};
+    for (u32 c : u.order) key.push_back(c);
+    key.push_back(0xffffffffull);
+    for (size_t p = 0; p < u.pos_var.size(); ++p) {
+      if (u.pos_var[p] < 0) key.push_back(((u64)1 << 40) | u.pos_const[p]);
+      else if (level_of[u.pos_var[p]] <= b) key.push_back(u.pos_var[p]);
+    }
+    return key;
+  };
+  auto consumed = [&](size_t ai, int b) {
+    u32 c = 0;
+    for (int pv : v.atoms[ai].pos_var)
+      if (pv >= 0 && level_of[pv] <= b) ++c;
+    return c;
+  };
+  auto nvarcols = [&](size_t ai) {
+    u32 c = 0;
+    for (int pv : v.atoms[ai].pos_var)
+      if (pv >= 0) ++c;
+    return c;
+  };
+  for (u32 b = 0; b < m; ++b) {
+    std::vector<std::vector<u64>> keys;
+    P.nslot[b] = 0;
+    for (u32 ai = 0; ai < (u32)MAXN; ++ai) P.atom_slot[b][ai] = NONE, P.slot_atom[b][ai] = NONE;
+    for (size_t ai = 0; ai < v.atoms.size(); ++ai) {
+      const u32 cb = consumed(ai, (int)b);
+      if (cb == 0 || cb == nvarcols(ai)) continue;  // unnarrowed, or closed
+      auto key = range_key(ai, (int)b);
+      size_t k = std::find(keys.begin(), keys.end(), key) - keys.begin();
+      if (k == keys.size()) {
+        keys.push_back(key);
+        P.slot_atom[b][k] = (u32)ai;
+        P.nslot[b]++;
+      }
+      P.atom_slot[b][ai] = (u32)k;
+    }
+  }
+  for (u32 L = 0; L < m; ++L) {
+    DLevel& lv = P.lvl[L];
+    for (u32 s2 = 0; s2 < lv.nsrc; ++s2) {
+      DSource& src = lv.src[s2];
+      src.alias = NONE;
+      src.dir = nullptr;
+      src.dmax = 0;
+      const size_t ai = src.atom;
+      auto k2 = range_key(ai, (int)L - 1);
+      for (u32 s1 = 0; s1 < s2 && src.alias == NONE; ++s1)
+        if (range_key(lv.src[s1].atom, (int)L - 1) == k2) src.alias = s1;
+    }
+  }
   // Root: the delta atom's source at level 0 if it has one there, else the
   // first level-0 source.
   {
     const DLevel& l0 = P.lvl[0];
     P.root_src = 0;
     if (delta_atom >= 0 && l0.atom_src[delta_atom] != NONE) P.root_src = l0.atom_src[delta_atom];
+  }
+  // Sources read through a dense directory: the first column of a copy that
+  // nothing has narrowed yet (no constants, no earlier variable).
+  v.want_dir.assign(m, {});
+  for (u32 L = 0; L < m; ++L) {
+    const DLevel& lv = P.lvl[L];
+    for (u32 s2 = 0; s2 < lv.nsrc; ++s2) {
+      const DSource& src = lv.src[s2];
+      bool want = v.src_pos[L][s2] == 0 && v.atoms[src.atom].nconst == 0 && src.alias == NONE &&
+                  !(L == 0 && s2 == P.root_src);
+      v.want_dir[L].push_back(want);
+    }
   }
   // Head.
   P.head_arity = (u32)r.head.t.size();
@@ -648,8 +717,8 @@ Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
     u32 w = 0;
     for (u32 b = 0; b + 1 < m; ++b) {
       P.off_val[b] = w; w += (b + 1) * cap;
-      P.off_lo[b] = w; w += P.natoms * cap;
-      P.off_hi[b] = w; w += P.natoms * cap;
+      P.off_lo[b] = w; w += P.nslot[b] * cap;
+      P.off_hi[b] = w; w += P.nslot[b] * cap;
       P.off_drv[b] = w; w += cap;
       P.off_clo[b] = w; w += cap;
       P.off_chi[b] = w; w += cap;
@@ -658,6 +727,7 @@ Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
     }
     return w;
   };
+  // Keep at least three workgroups resident per CU where possible.
   u32 cap = 512;
   u32 words = layout(cap);
   if (words * 4 > LDS_BUDGET) {
@@ -726,6 +796,7 @@ struct Stats {
   double kernel_ms[4] = {0};
   u64 launches[4] = {0};
   u64 examined = 0;
+  u64 exam_level[MAXV] = {0};
 };
 
 // HIP events around one kernel launch on its stream; read after a sync.
@@ -762,9 +833,25 @@ double ms_since(Clock::time_point t) {
   return std::chrono::duration<double, std::milli>(Clock::now() - t).count();
 }
 
+// Dense directory over column 0 of a copy, when its values are dense enough
+// (largest value at most 4 rows per row plus slack).  Built once per copy.
+void ensure_directory(Engine* e, Cols& c) {
+  if (c.dir_tried || c.n == 0) return;
+  c.dir_tried = true;
+  // The copy may still be being written on stream 0: read it there.
+  u32 vmax = 0;
+  WCDL_HIP(hipMemcpyAsync(&vmax, c.col[0].get() + (c.n - 1), sizeof(u32), hipMemcpyDeviceToHost,
+                          e->streams[0]));
+  WCDL_HIP(hipStreamSynchronize(e->streams[0]));
+  if ((u64)vmax > 4 * c.n + 4096) return;
+  c.dir = DBuf<u32>(e->mem.get(), (u64)vmax + 2);
+  c.dir_max = vmax;
+  build_directory(ctx(e), c.col[0].get(), c.n, vmax, c.dir.get());
+}
+
 // The sorted copy of (relation, delta?, order) a version reads; built on
 // demand from the canonical copy.
-const Cols& get_cols(Engine* e, u32 rel, bool delta, const std::vector<u32>& order) {
+Cols& get_cols(Engine* e, u32 rel, bool delta, const std::vector<u32>& order) {
   Relation& R = e->rels[rel];
   const std::vector<u32> canon = canonical(R.arity);
   if (!delta) {
@@ -796,6 +883,7 @@ struct VRun {
   DBuf<u64> W, C;
   DBuf<u32> klo, kd;
   DBuf<u64> counts, offsets;
+  DBuf<u64> cand;  // candidates examined per level (materialize)
   DBuf<u64> scal;  // [0] K, [1] T, [2] total, [3] materialize error flag
   u64 K = 0, T = 0, total = 0;
   u64 out_off = 0;
@@ -839,12 +927,25 @@ std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
     DPlan& P = v.plan;
     for (size_t ai = 0; ai < v.atoms.size(); ++ai) {
       const AtomUse& u = v.atoms[ai];
-      const Cols& cc = get_cols(e, u.rel, u.delta, u.order);
+      Cols& cc = get_cols(e, u.rel, u.delta, u.order);
       if (cc.n == 0) R.skip = true;
       if (cc.n >= 0xffffffffull) throw Error(WCDL_E_UNSUPPORTED, "join source exceeds 2^32-1 rows");
       P.atom_n[ai] = (u32)cc.n;
       for (size_t p = 0; p < u.order.size(); ++p) P.atom_col[ai][p] = cc.col[p].get();
     }
+    for (u32 L = 0; L < P.m && !R.skip; ++L)
+      for (u32 s2 = 0; s2 < P.lvl[L].nsrc; ++s2) {
+        DSource& src = P.lvl[L].src[s2];
+        src.dir = nullptr;
+        if (!v.want_dir[L][s2]) continue;
+        const AtomUse& u = v.atoms[src.atom];
+        Cols& cc = get_cols(e, u.rel, u.delta, u.order);
+        ensure_directory(e, cc);
+        if (cc.dir.get()) {
+          src.dir = cc.dir.get();
+          src.dmax = cc.dir_max;
+        }
+      }
   }
   WCDL_HIP(hipStreamSynchronize(e->streams[0]));
   // ---- Phase A: plan upload, constant narrowing, root-key flags.
@@ -919,7 +1020,7 @@ std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
       p = R.K;  // one root key per workgroup (the unbalanced baseline)
       R.part = Partition{p, 0, 1, 0};
     } else {
-      const u64 wpc = e->cfg.wg_per_cu ? e->cfg.wg_per_cu : 8;
+      const u64 wpc = e->cfg.wg_per_cu ? e->cfg.wg_per_cu : 32;
       p = std::min<u64>(ceil_div(R.T, 64), NCU * wpc);
       if (p == 0) p = 1;
       const u64 slice = ceil_div(R.T, p);
@@ -971,8 +1072,9 @@ std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
     for (u32 h = 0; h < P.head_arity; ++h) P.out[h] = dst.col[h].get() + R.out_off;
     P.out_rows = R.total;
     P.err = reinterpret_cast<u32*>(R.scal.get() + 3);
-    P.cand = R.scal.get() + 2;  // reused: the total was read already
-    fill_u64(c, R.scal.get() + 2, 1, 0);
+    R.cand = DBuf<u64>(c.mem, MAXV);
+    fill_u64(c, R.cand.get(), MAXV, 0);
+    P.cand = R.cand.get();
     *R.host_plan = P;
     WCDL_HIP(hipMemcpyAsync(R.d_plan.get(), R.host_plan, sizeof(DPlan), hipMemcpyHostToDevice, c.s));
     R.t_mat.start(c.s, 1);
@@ -987,11 +1089,19 @@ std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
   sync_all(e);
   for (auto& R : runs) {
     if (R.skip) continue;
-    u64 flag = 0, examined = 0;
+    u64 flag = 0, lv[MAXV];
     WCDL_HIP(hipMemcpy(&flag, R.scal.get() + 3, sizeof(u64), hipMemcpyDeviceToHost));
     if (flag) throw Error(WCDL_E_DEVICE, "internal error: materialize produced more rows than counted");
-    WCDL_HIP(hipMemcpy(&examined, R.scal.get() + 2, sizeof(u64), hipMemcpyDeviceToHost));
-    st.examined += R.v->plan.xprod ? R.total : examined;
+    WCDL_HIP(hipMemcpy(lv, R.cand.get(), sizeof(lv), hipMemcpyDeviceToHost));
+    if (R.v->plan.xprod) {
+      st.examined += R.total;
+      st.exam_level[R.v->plan.m - 1] += R.total;
+    } else {
+      for (int j = 0; j < MAXV; ++j) {
+        st.examined += lv[j];
+        st.exam_level[j] += lv[j];
+      }
+    }
   }
   for (auto& R : runs) {
     R.t_hist.collect(st);
@@ -1128,6 +1238,7 @@ void run_program(Engine* e, wcdl_run_stats* stats_out) {
     s.kernel_launches[i] = st.launches[i];
   }
   s.candidates_checked = st.examined;
+  for (int j = 0; j < MAXV; ++j) s.candidates_per_level[j] = st.exam_level[j];
   e->last = s;
   if (stats_out) *stats_out = s;
 }

@@ -109,6 +109,9 @@ struct Cols {
   std::vector<u32> order;
   std::vector<DBuf<u32>> col;
   u64 n = 0;
+  DBuf<u32> dir;       // dense directory of column 0 (built on demand)
+  u32 dir_max = 0;
+  bool dir_tried = false;
   u32 arity() const { return (u32)order.size(); }
   std::vector<const u32*> ptrs() const {
     std::vector<const u32*> v;
@@ -137,8 +140,13 @@ struct DOperand {
 
 struct DSource {      // an atom constraining the level's variable
   const u32* col;     // the atom's column holding this variable
-  u32 atom;           // atom index (range slot)
+  const u32* dir;     // optional dense directory of col (first column of a copy
+                      // read unnarrowed): rows of value v are [dir[v], dir[v+1])
+  u32 dmax;           // largest value covered by dir
+  u32 atom;           // atom index
   u32 last;           // 1 if no variable column of the atom follows
+  u32 alias;          // earlier source at this level with the same column and
+                      // the same current range (its result is reused), or NONE
 };
 
 struct DBound {       // x_level >= opnd + adj (lo) or x_level <= opnd - adj (hi)
@@ -170,12 +178,20 @@ struct DPlan {
   u32* out[MAXA];         // output columns (materialize)
   u64 out_rows;           // rows reserved at out[] (writes beyond are refused)
   u32* err;               // device flag set if a write was refused
-  u64* cand;              // optional: candidates examined (materialize pass)
+  u64* cand;              // optional: candidates examined per level (materialize)
   u32 atom_n[MAXN];       // rows in each atom's sorted copy
   u32 atom_nconst[MAXN];  // leading constant columns of each atom
   u32 atom_const[MAXN][MAXA];
   const u32* atom_col[MAXN][MAXA];
   DLevel lvl[MAXV];
+  // Range slots of the level buffers.  After binding level b, atoms whose
+  // ranges are equal share a slot; atom_slot[b][a] is NONE for an atom not
+  // narrowed yet (its range is its constant-narrowed initial range) or no
+  // longer needed (all its columns bound).  slot_atom[b][s] is an atom whose
+  // range the slot holds.
+  u32 nslot[MAXV];
+  u32 atom_slot[MAXV][MAXN];
+  u32 slot_atom[MAXV][MAXN];
   // Shared-memory layout of the level buffers (offsets in 32-bit words).
   u32 cap;                // items per level buffer
   u32 off_val[MAXV], off_lo[MAXV], off_hi[MAXV], off_drv[MAXV], off_clo[MAXV],
@@ -256,6 +272,9 @@ void join_histogram(Ctx c, const DPlan* d_plan, const RootSpace& rs, u64* W, u32
 // Count (mode 0) or materialize (mode 1) over workgroups [wg0, wg0+nwg).
 void join_run(Ctx c, const DPlan* d_plan, const RootSpace& rs, const Partition& part,
               u32 lds_bytes, int mode, u64* counts, const u64* offsets, u64 wg0, u64 nwg);
+// Dense directory of a sorted column with values <= vmax: dir[v] = first row
+// with value >= v, for v in [0, vmax+1] (vmax + 2 entries).
+void build_directory(Ctx c, const u32* col, u64 n, u32 vmax, u32* dir);
 // Cross-product decode path: writes T rows directly.
 void join_xprod(Ctx c, const DPlan* d_plan, const RootSpace& rs, const u32* klo, const u32* kd,
                 u32 m);

@@ -128,8 +128,14 @@ struct Bufs {
   u32* sm;
   const DPlan* P;
   const u32* rng0;  // [2*MAXN] in LDS
-  __device__ u32 lo(int b, u32 a, u32 i) const { return b < 0 ? rng0[2 * a] : sm[P->off_lo[b] + a * P->cap + i]; }
-  __device__ u32 hi(int b, u32 a, u32 i) const { return b < 0 ? rng0[2 * a + 1] : sm[P->off_hi[b] + a * P->cap + i]; }
+  __device__ u32 lo(int b, u32 a, u32 i) const {
+    const u32 s = b < 0 ? NONE : P->atom_slot[b][a];
+    return s == NONE ? rng0[2 * a] : sm[P->off_lo[b] + s * P->cap + i];
+  }
+  __device__ u32 hi(int b, u32 a, u32 i) const {
+    const u32 s = b < 0 ? NONE : P->atom_slot[b][a];
+    return s == NONE ? rng0[2 * a + 1] : sm[P->off_hi[b] + s * P->cap + i];
+  }
   __device__ u32 val(int b, u32 k, u32 i) const { return sm[P->off_val[b] + k * P->cap + i]; }
 };
 
@@ -151,6 +157,9 @@ __device__ inline bool try_candidate(const DPlan* P, const Bufs& B, int L, u32 i
   for (u32 f = 0; f < lv.nne; ++f)
     if (v == operand(B, lv.ne[f], L, i, v)) return false;
   if (L == 0) {
+    // An atom without matches under its constants empties the rule.
+    for (u32 a = 0; a < P->natoms; ++a)
+      if (B.rng0[2 * a] >= B.rng0[2 * a + 1]) return false;
     // Level-0 values come straight from the root keys, so their bounds
     // (constants only) are checked here; deeper levels clip candidate
     // ranges to their bounds instead (prepare_item).
@@ -166,16 +175,34 @@ __device__ inline bool try_candidate(const DPlan* P, const Bufs& B, int L, u32 i
 #pragma unroll
   for (int s = 0; s < MAXS; ++s) {
     if (s < (int)lv.nsrc) {
-      const u32* col = lv.src[s].col;
-      const u32 a = lv.src[s].atom;
-      const bool last = lv.src[s].last != 0;
-      u32 lo = B.lo(L - 1, a, i), hi = B.hi(L - 1, a, i);
+      const DSource& src = lv.src[s];
+      const u32* col = src.col;
+      const u32 a = src.atom;
+      const bool last = src.last != 0;
+      u32 lo, hi;
       if ((u32)s == drv) {
+        lo = B.lo(L - 1, a, i);
         // Only the first row of a run of equal values yields the candidate.
         if (!last && r > lo && col[r - 1] == v) return false;
+        hi = B.hi(L - 1, a, i);
         lo = r;
-        hi = last ? r + 1 : (dhi != NONE ? dhi : gallop_past(col, r + 1, hi, v));
+        if (last) hi = r + 1;
+        else if (dhi != NONE) hi = dhi;
+        else if (src.dir) hi = src.dir[v + 1];
+        else hi = gallop_past(col, r + 1, hi, v);
+      } else if (src.alias != NONE) {
+        // Same column and same range as an earlier source: same result.
+        lo = slo.get(src.alias);
+        hi = shi.get(src.alias);
+      } else if (src.dir) {
+        // Unnarrowed first column: the directory gives the run directly.
+        if (v > src.dmax) return false;
+        lo = src.dir[v];
+        hi = src.dir[v + 1];
+        if (lo >= hi) return false;
       } else {
+        lo = B.lo(L - 1, a, i);
+        hi = B.hi(L - 1, a, i);
         u32 p = lower_bound_u32(col, lo, hi, v);
         if (p >= hi || col[p] != v) return false;
         lo = p;
@@ -207,11 +234,6 @@ __device__ inline void new_range(const DPlan* P, const Bufs& B, int L, u32 i, u3
 __device__ inline bool prepare_item(const DPlan* P, const Bufs& B, int L, u32 i, u32 v,
                                     const R8& slo, const R8& shi, u32* drv,
                                     u32* clo, u32* chi) {
-  for (u32 a = 0; a < P->natoms; ++a) {
-    u32 lo, hi;
-    new_range(P, B, L, i, a, slo, shi, &lo, &hi);
-    if (lo >= hi) return false;
-  }
   const DLevel& nx = P->lvl[L + 1];
   u32 best = 0, bsz = UMAX, blo = 0, bhi = 0;
   for (u32 s = 0; s < nx.nsrc; ++s) {
@@ -254,11 +276,11 @@ __device__ inline void store_item(const DPlan* P, const Bufs& B, int L, u32 i, u
   u32* sm = B.sm;
   for (int k = 0; k < L; ++k) sm[P->off_val[L] + k * cap + pos] = B.val(L - 1, k, i);
   sm[P->off_val[L] + L * cap + pos] = v;
-  for (u32 a = 0; a < P->natoms; ++a) {
+  for (u32 t = 0; t < P->nslot[L]; ++t) {
     u32 lo, hi;
-    new_range(P, B, L, i, a, slo, shi, &lo, &hi);
-    sm[P->off_lo[L] + a * cap + pos] = lo;
-    sm[P->off_hi[L] + a * cap + pos] = hi;
+    new_range(P, B, L, i, P->slot_atom[L][t], slo, shi, &lo, &hi);
+    sm[P->off_lo[L] + t * cap + pos] = lo;
+    sm[P->off_hi[L] + t * cap + pos] = hi;
   }
   sm[P->off_drv[L] + pos] = drv;
   sm[P->off_clo[L] + pos] = clo;
@@ -279,7 +301,7 @@ struct WgState {
   u64 cur[MAXV];      // candidates consumed
   u64 out;            // rows counted / written so far
   u64 key_next;       // next root key to turn into a level-0 item
-  u64 examined;       // candidates examined by this workgroup
+  u64 exam[MAXV];     // candidates examined by this workgroup, per level
   u32 rng0[2 * MAXN];
   u64 sh[WG / 64];
 };
@@ -306,7 +328,7 @@ __device__ void finalize_buffer(const DPlan* P, u32* sm, WgState& st, int b) {
   if (threadIdx.x == 0) {
     st.total[b] = tot;
     st.cur[b] = 0;
-    st.examined += tot;
+    st.exam[b + 1] += tot;
   }
   __syncthreads();
 }
@@ -342,7 +364,8 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
   if (threadIdx.x == 0) {
     st.key_next = kfirst;
     st.out = 0;
-    st.examined = 0;
+    for (int j = 0; j < MAXV; ++j) st.exam[j] = 0;
+    st.exam[0] = klast - kfirst + 1;
     for (int j = 0; j < MAXV; ++j) st.n[j] = 0, st.total[j] = 0, st.cur[j] = 0;
   }
   __syncthreads();
@@ -501,8 +524,9 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
     u64 tot;
     block_excl_scan(my_count, st.sh, &tot);
     if (threadIdx.x == 0) counts[b] = tot;
-  } else if (P->cand && threadIdx.x == 0) {
-    atomicAdd(reinterpret_cast<unsigned long long*>(P->cand), (unsigned long long)st.examined);
+  } else if (P->cand && threadIdx.x < P->m) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(P->cand + threadIdx.x),
+              (unsigned long long)st.exam[threadIdx.x]);
   }
 }
 
@@ -525,11 +549,6 @@ __global__ __launch_bounds__(WG) void k_hist(const DPlan* __restrict__ P, RootSp
     } else if (xprod) {
       // Cross product of independent single-source levels: W = prod d_j.
       w = 1;
-      for (u32 a = 0; a < P->natoms && w; ++a) {
-        u32 lo, hi;
-        new_range(P, B, 0, 0, a, slo, shi, &lo, &hi);
-        if (lo >= hi) w = 0;
-      }
       for (u32 j = 1; j < P->m && w; ++j) {
         u32 lo, hi;
         new_range(P, B, 0, 0, P->lvl[j].src[0].atom, slo, shi, &lo, &hi);
@@ -636,6 +655,18 @@ __global__ __launch_bounds__(WG) void k_key_compact(const u32* col, const u32* f
 
 __global__ void k_key_end(const u32* rng0, u32 atom, u64 K, u32* S) { S[K] = rng0[2 * atom + 1]; }
 
+// dir[v] = first row with value >= v.  Row r writes the entries for the
+// values in (col[r-1], col[r]]; the last row also writes (col[n-1], vmax+1].
+__global__ __launch_bounds__(WG) void k_build_dir(const u32* col, u64 n, u32 vmax, u32* dir) {
+  const u64 r = (u64)blockIdx.x * WG + threadIdx.x;
+  if (r >= n) return;
+  const u32 v = col[r];
+  const u64 from = r ? (u64)col[r - 1] + 1 : 0;
+  for (u64 u = from; u <= v && u <= vmax; ++u) dir[u] = (u32)r;
+  if (r == n - 1)
+    for (u64 u = (u64)v + 1; u <= (u64)vmax + 1; ++u) dir[u] = (u32)n;
+}
+
 u32 grid1(u64 n) {
   u64 g = ceil_div(n, WG);
   if (g > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "grid too large");
@@ -668,6 +699,12 @@ void join_root_compact(Ctx c, const u32* col, const u32* d_rng0, u32 atom, u32 n
     WCDL_HIP(hipGetLastError());
   }
   k_key_end<<<1, 1, 0, c.s>>>(d_rng0, atom, K, S);
+  WCDL_HIP(hipGetLastError());
+}
+
+void build_directory(Ctx c, const u32* col, u64 n, u32 vmax, u32* dir) {
+  if (n == 0) return;
+  k_build_dir<<<grid1(n), WG, 0, c.s>>>(col, n, vmax, dir);
   WCDL_HIP(hipGetLastError());
 }
 

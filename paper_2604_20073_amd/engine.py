@@ -53,7 +53,8 @@ class _Stats(ctypes.Structure):
                 ("candidate_rows", ctypes.c_uint64), ("join_units", ctypes.c_uint64),
                 ("wall_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 8),
                 ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_uint64 * 4),
-                ("candidates_checked", ctypes.c_uint64)]
+                ("candidates_checked", ctypes.c_uint64),
+                ("candidates_per_level", ctypes.c_uint64 * 8)]
 
 
 class WcdlError(RuntimeError):
@@ -267,7 +268,8 @@ class Engine:
                 "wall_ms": s.wall_ms, "phase_ms": dict(zip(PHASES, list(s.phase_ms))),
                 "kernel_ms": dict(zip(KERNELS, list(s.kernel_ms))),
                 "kernel_launches": dict(zip(KERNELS, [int(x) for x in s.kernel_launches])),
-                "candidates_checked": s.candidates_checked}
+                "candidates_checked": s.candidates_checked,
+                "candidates_per_level": [int(x) for x in s.candidates_per_level]}
 
     def size(self, name: str) -> int:
         n = ctypes.c_uint64()
