@@ -70,6 +70,8 @@ typedef int32_t wcdl_status;
 #define WCDL_F_XPROD_OFF 0x4u    /* disable the per-unit decode fast path for
                                     cross-product plans (Sec. 5, work-unit
                                     decode); use the general kernel instead */
+#define WCDL_F_STAGE_OFF 0x8u    /* never stage rows during the count pass: the
+                                    write pass always re-runs the traversal */
 
 typedef struct wcdl_engine wcdl_engine;
 
@@ -96,6 +98,10 @@ typedef struct {
   uint32_t flags;            /* WCDL_F_* */
   uint32_t wg_per_cu;        /* work-partition oversubscription: p = 256 CUs x
                                 wg_per_cu workgroups per join; 0 = default (32) */
+  uint32_t stage_pct;        /* count-pass staging arena, in percent of the rows
+                                a rule version produced per work unit last time
+                                (0 = default 125).  Rows that do not fit are
+                                recomputed by the write pass. */
 } wcdl_config;
 
 /* Fill `cfg` with defaults (device 0, own streams, hipMalloc, no budget). */

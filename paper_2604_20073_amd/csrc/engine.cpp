@@ -228,6 +228,9 @@ struct wcdl_engine {
   uint64_t* pinned = nullptr;  // host-pinned scratch for device->host scalars
   uint32_t helper_count = 0;
   wcdl_run_stats last{};
+  // Rows produced per work unit by each rule version (rule, delta atom) the
+  // last time it ran; sizes the count-pass staging arena.
+  std::map<std::pair<uint32_t, int>, double> rows_per_unit;
 };
 
 namespace wcdl {
@@ -884,6 +887,13 @@ struct VRun {
   DBuf<u32> klo, kd;
   DBuf<u64> counts, offsets;
   DBuf<u64> cand;  // candidates examined per level (materialize)
+  bool staged = false;
+  std::vector<DBuf<u32>> stage;
+  DBuf<u64> chunk_tag, stage_next;
+  DBuf<u32> ovf;
+  u64 stage_chunks = 0, used_chunks = 0;
+  std::vector<u32> overflowed;
+  DBuf<u32> d_overflowed;
   DBuf<u64> scal;  // [0] K, [1] T, [2] total, [3] materialize error flag
   u64 K = 0, T = 0, total = 0;
   u64 out_off = 0;
@@ -1029,8 +1039,53 @@ std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
     }
     R.counts = DBuf<u64>(c.mem, p);
     R.offsets = DBuf<u64>(c.mem, p);
+    // Stage rows during the count pass when the previous run of this rule
+    // version tells how many to expect.
+    auto key = std::make_pair(R.v->rule, R.v->delta_atom);
+    auto rit = e->rows_per_unit.find(key);
+    if (!(flags & WCDL_F_STAGE_OFF) && rit != e->rows_per_unit.end()) {
+      const double pct = e->cfg.stage_pct ? e->cfg.stage_pct : 125;
+      const u32 k = P.head_arity;
+      u64 est = (u64)((double)R.T * rit->second * pct / 100.0) + STAGE_CHUNK * p;
+      u64 chunks = ceil_div(est, STAGE_CHUNK);
+      size_t free_b = 0, total_b = 0;
+      WCDL_HIP(hipMemGetInfo(&free_b, &total_b));
+      const u64 limit = std::min<u64>((u64)(total_b * 0.4), e->cfg.mem_budget_bytes
+                                                                ? e->cfg.mem_budget_bytes / 4
+                                                                : ~0ull);
+      const u64 per_chunk = STAGE_CHUNK * k * 4ull;
+      chunks = std::min<u64>(chunks, limit / per_chunk);
+      if (chunks > 0) {
+        try {
+          for (u32 h = 0; h < k; ++h) R.stage.emplace_back(c.mem, chunks * STAGE_CHUNK);
+          R.chunk_tag = DBuf<u64>(c.mem, chunks);
+          R.stage_next = DBuf<u64>(c.mem, 1);
+          R.ovf = DBuf<u32>(c.mem, p);
+          R.staged = true;
+          R.stage_chunks = chunks;
+        } catch (const Error& x) {
+          if (x.code != WCDL_E_NOMEM) throw;
+          R.stage.clear();  // not enough memory: plain two passes
+        }
+      }
+    }
+    if (R.staged) {
+      DPlan& PM = R.v->plan;
+      R.cand = DBuf<u64>(c.mem, MAXV);
+      fill_u64(c, R.cand.get(), MAXV, 0);
+      PM.cand = R.cand.get();  // the staged count pass does the full traversal
+      for (u32 h = 0; h < PM.head_arity; ++h) PM.stage[h] = R.stage[h].get();
+      PM.stage_chunks = R.stage_chunks;
+      PM.stage_next = R.stage_next.get();
+      PM.chunk_tag = R.chunk_tag.get();
+      PM.ovf = R.ovf.get();
+      fill_u64(c, R.stage_next.get(), 1, 0);
+      *R.host_plan = PM;
+      WCDL_HIP(hipMemcpyAsync(R.d_plan.get(), R.host_plan, sizeof(DPlan), hipMemcpyHostToDevice, c.s));
+    }
     R.t_count.start(c.s, 0);
-    join_run(c, R.d_plan.get(), R.rs, R.part, R.v->lds_bytes, 0, R.counts.get(), nullptr, 0, p);
+    join_run(c, R.d_plan.get(), R.rs, R.part, R.v->lds_bytes, R.staged ? 2 : 0, R.counts.get(),
+             nullptr, 0, p);
     R.t_count.stop(c.s);
     scan_u64_excl(c, R.counts.get(), R.offsets.get(), p, R.scal.get() + 2);
   }
@@ -1038,6 +1093,15 @@ std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
   for (auto& R : runs) {
     if (R.skip || R.v->plan.xprod) continue;
     WCDL_HIP(hipMemcpy(&R.total, R.scal.get() + 2, sizeof(u64), hipMemcpyDeviceToHost));
+    e->rows_per_unit[std::make_pair(R.v->rule, R.v->delta_atom)] = (double)R.total / (double)R.T;
+    if (R.staged) {
+      WCDL_HIP(hipMemcpy(&R.used_chunks, R.stage_next.get(), sizeof(u64), hipMemcpyDeviceToHost));
+      R.used_chunks = std::min(R.used_chunks, R.stage_chunks);
+      std::vector<u32> ovf(R.part.p);
+      WCDL_HIP(hipMemcpy(ovf.data(), R.ovf.get(), R.part.p * sizeof(u32), hipMemcpyDeviceToHost));
+      for (u32 b = 0; b < R.part.p; ++b)
+        if (ovf[b]) R.overflowed.push_back(b);
+    }
     if (R.total == 0) R.skip = true;
   }
   st.phase[WCDL_PH_COUNT] += ms_since(t_count);
@@ -1072,17 +1136,34 @@ std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
     for (u32 h = 0; h < P.head_arity; ++h) P.out[h] = dst.col[h].get() + R.out_off;
     P.out_rows = R.total;
     P.err = reinterpret_cast<u32*>(R.scal.get() + 3);
-    R.cand = DBuf<u64>(c.mem, MAXV);
-    fill_u64(c, R.cand.get(), MAXV, 0);
-    P.cand = R.cand.get();
+    if (R.staged) {
+      P.cand = nullptr;  // counted in the staged count pass
+    } else {
+      R.cand = DBuf<u64>(c.mem, MAXV);
+      fill_u64(c, R.cand.get(), MAXV, 0);
+      P.cand = R.cand.get();
+    }
     *R.host_plan = P;
     WCDL_HIP(hipMemcpyAsync(R.d_plan.get(), R.host_plan, sizeof(DPlan), hipMemcpyHostToDevice, c.s));
     R.t_mat.start(c.s, 1);
-    if (P.xprod)
+    if (P.xprod) {
       join_xprod(c, R.d_plan.get(), R.rs, R.klo.get(), R.kd.get(), P.m);
-    else
+    } else if (R.staged) {
+      // Staged rows: copy to their offsets; re-run only workgroups whose
+      // rows did not all fit in the arena.
+      join_stage_copy(c, R.d_plan.get(), R.used_chunks, R.counts.get(), R.offsets.get(),
+                      P.head_arity);
+      if (!R.overflowed.empty()) {
+        R.d_overflowed = DBuf<u32>(c.mem, R.overflowed.size());
+        WCDL_HIP(hipMemcpyAsync(R.d_overflowed.get(), R.overflowed.data(),
+                                R.overflowed.size() * sizeof(u32), hipMemcpyHostToDevice, c.s));
+        join_run(c, R.d_plan.get(), R.rs, R.part, R.v->lds_bytes, 1, nullptr, R.offsets.get(), 0,
+                 R.overflowed.size(), R.d_overflowed.get());
+      }
+    } else {
       join_run(c, R.d_plan.get(), R.rs, R.part, R.v->lds_bytes, 1, nullptr, R.offsets.get(), 0,
                R.part.p);
+    }
     R.t_mat.stop(c.s);
     st.candidates += R.total;
   }

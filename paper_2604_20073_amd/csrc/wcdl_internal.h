@@ -179,6 +179,14 @@ struct DPlan {
   u64 out_rows;           // rows reserved at out[] (writes beyond are refused)
   u32* err;               // device flag set if a write was refused
   u64* cand;              // optional: candidates examined per level (materialize)
+  // Staging of the count pass (mode 2): rows go to an arena of chunks of
+  // STAGE_CHUNK rows taken from a global counter; chunk_tag[c] = (workgroup
+  // << 32) | sequence number of the chunk within that workgroup's rows.
+  u32* stage[MAXA];
+  u64 stage_chunks;       // arena capacity in chunks
+  u64* stage_next;        // chunks handed out so far
+  u64* chunk_tag;
+  u32* ovf;               // per workgroup: 1 if its rows did not all fit
   u32 atom_n[MAXN];       // rows in each atom's sorted copy
   u32 atom_nconst[MAXN];  // leading constant columns of each atom
   u32 atom_const[MAXN][MAXA];
@@ -269,9 +277,16 @@ void join_root_compact(Ctx c, const u32* col, const u32* d_rng0, u32 atom, u32 n
 // per-key (lo, size) of every level >= 1 into klo/kd ([m][K]).
 void join_histogram(Ctx c, const DPlan* d_plan, const RootSpace& rs, u64* W, u32* klo, u32* kd,
                     u32 m);
-// Count (mode 0) or materialize (mode 1) over workgroups [wg0, wg0+nwg).
+constexpr u64 STAGE_CHUNK = 4096;
+// Count (mode 0), materialize (mode 1) or count-and-stage (mode 2) over
+// workgroups wg0 + [0, nwg), or over the listed workgroups if wg_list is set.
 void join_run(Ctx c, const DPlan* d_plan, const RootSpace& rs, const Partition& part,
-              u32 lds_bytes, int mode, u64* counts, const u64* offsets, u64 wg0, u64 nwg);
+              u32 lds_bytes, int mode, u64* counts, const u64* offsets, u64 wg0, u64 nwg,
+              const u32* wg_list = nullptr);
+// Write pass for staged rows: chunk c of workgroup b goes to
+// offsets[b] + seq * STAGE_CHUNK unless b overflowed.
+void join_stage_copy(Ctx c, const DPlan* d_plan, u64 used_chunks, const u64* counts,
+                     const u64* offsets, u32 arity);
 // Dense directory of a sorted column with values <= vmax: dir[v] = first row
 // with value >= v, for v in [0, vmax+1] (vmax + 2 entries).
 void build_directory(Ctx c, const u32* col, u64 n, u32 vmax, u32* dir);

@@ -228,24 +228,12 @@ __device__ inline void new_range(const DPlan* P, const Bufs& B, int L, u32 i, u3
   }
 }
 
-// After binding level L: every atom must still match something; choose the
-// level L+1 driver (smallest range) and clip its range to the value bounds of
-// level L+1.  Yields the candidate rows [clo, chi) of the new item.
+// After binding level L: choose the driver of level L+1 -- the source whose
+// range, clipped to the value bounds of level L+1, is smallest -- and yield
+// its clipped candidate rows [clo, chi) for the new item.
 __device__ inline bool prepare_item(const DPlan* P, const Bufs& B, int L, u32 i, u32 v,
-                                    const R8& slo, const R8& shi, u32* drv,
-                                    u32* clo, u32* chi) {
+                                    const R8& slo, const R8& shi, u32* drv, u32* clo, u32* chi) {
   const DLevel& nx = P->lvl[L + 1];
-  u32 best = 0, bsz = UMAX, blo = 0, bhi = 0;
-  for (u32 s = 0; s < nx.nsrc; ++s) {
-    u32 lo, hi;
-    new_range(P, B, L, i, nx.src[s].atom, slo, shi, &lo, &hi);
-    if (hi - lo < bsz) {
-      bsz = hi - lo;
-      best = s;
-      blo = lo;
-      bhi = hi;
-    }
-  }
   u32 lov = 0, hiv = UMAX;
   for (u32 b = 0; b < nx.nbnd; ++b) {
     u32 x = operand(B, nx.bnd[b].o, L, i, v);
@@ -259,13 +247,34 @@ __device__ inline bool prepare_item(const DPlan* P, const Bufs& B, int L, u32 i,
     }
   }
   if (lov > hiv) return false;
-  const u32* col = nx.src[best].col;
-  u32 lo = lov ? lower_bound_u32(col, blo, bhi, lov) : blo;
-  u32 hi = (hiv != UMAX) ? upper_bound_u32(col, lo, bhi, hiv) : bhi;
-  if (lo >= hi) return false;
+  const bool clip = lov != 0 || hiv != UMAX;
+  u32 best = 0, bsz = UMAX, blo = 0, bhi = 0;
+  for (u32 s = 0; s < nx.nsrc; ++s) {
+    if (nx.src[s].alias != NONE) continue;  // same range as an earlier source
+    u32 lo, hi;
+    new_range(P, B, L, i, nx.src[s].atom, slo, shi, &lo, &hi);
+    if (clip) {
+      const DSource& src = nx.src[s];
+      if (src.dir) {
+        // Unnarrowed first column: clip through the directory.
+        if (lov) lo = lov <= src.dmax ? src.dir[lov] : hi;
+        if (hiv < src.dmax) hi = src.dir[hiv + 1];
+      } else {
+        if (lov) lo = lower_bound_u32(src.col, lo, hi, lov);
+        if (hiv != UMAX) hi = upper_bound_u32(src.col, lo, hi, hiv);
+      }
+    }
+    if (lo >= hi) return false;  // no value can satisfy this source
+    if (hi - lo < bsz) {
+      bsz = hi - lo;
+      best = s;
+      blo = lo;
+      bhi = hi;
+    }
+  }
   *drv = best;
-  *clo = lo;
-  *chi = hi;
+  *clo = blo;
+  *chi = bhi;
   return true;
 }
 
@@ -295,6 +304,10 @@ __device__ inline void emit_row(const DPlan* P, const Bufs& B, int L, u32 i, u32
   for (u32 h = 0; h < P->head_arity; ++h) P->out[h][at] = operand(B, P->head[h], L, i, v);
 }
 
+__device__ inline void stage_row(const DPlan* P, const Bufs& B, int L, u32 i, u32 v, u64 at) {
+  for (u32 h = 0; h < P->head_arity; ++h) P->stage[h][at] = operand(B, P->head[h], L, i, v);
+}
+
 struct WgState {
   u32 n[MAXV];        // items in each level buffer
   u64 total[MAXV];    // candidates of each level buffer
@@ -304,6 +317,9 @@ struct WgState {
   u64 exam[MAXV];     // candidates examined by this workgroup, per level
   u32 rng0[2 * MAXN];
   u64 sh[WG / 64];
+  u64 covered;        // staged rows for which chunks are held
+  u64 chunk[2];       // arena chunks holding the current and next row ranges
+  u32 ovf;            // staging arena exhausted for this workgroup
 };
 
 // Inclusive prefix of candidate counts of buffer b; sets total, resets cursor.
@@ -338,13 +354,52 @@ __device__ inline u64 rank_alive(bool alive, WgState& st, u64* tot) {
   return block_excl_scan(alive ? 1 : 0, st.sh, tot);
 }
 
+// One chunk of output candidates, called by every thread: count them
+// (mode 0), write them at their final offsets (mode 1), or count them and
+// stage them in arena chunks (mode 2).  Rows keep traversal order.
+template <int MODE>
+__device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, int L, u32 i,
+                                  u32 v, bool alive, u64 obase, u64 b, u64& my_count) {
+  if (MODE == 0) {
+    my_count += alive ? 1 : 0;
+    return;
+  }
+  u64 tot;
+  const u64 rk = rank_alive(alive, st, &tot);
+  if (MODE == 1) {
+    if (alive) emit_row(P, B, L, i, v, obase + st.out + rk);
+  } else {
+    if (threadIdx.x == 0 && !st.ovf && st.out + tot > st.covered) {
+      // tot <= WG <= STAGE_CHUNK: at most one new chunk per call.
+      const u64 c = atomicAdd(reinterpret_cast<unsigned long long*>(P->stage_next), 1ull);
+      if (c >= P->stage_chunks) {
+        st.ovf = 1;
+      } else {
+        const u64 seq = st.covered / STAGE_CHUNK;
+        P->chunk_tag[c] = (b << 32) | seq;
+        st.chunk[seq & 1] = c;
+        st.covered += STAGE_CHUNK;
+      }
+    }
+    __syncthreads();
+    if (alive && !st.ovf) {
+      const u64 r = st.out + rk;
+      const u64 c = st.chunk[(r / STAGE_CHUNK) & 1];
+      stage_row(P, B, L, i, v, c * STAGE_CHUNK + (r % STAGE_CHUNK));
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) st.out += tot;
+  __syncthreads();
+}
+
 template <int MODE>
 __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSpace rs,
                                              Partition part, u64* counts, const u64* offsets,
-                                             u64 wg0) {
+                                             u64 wg0, const u32* wg_list) {
   extern __shared__ __align__(16) u32 sm[];
   __shared__ WgState st;
-  const u64 b = wg0 + blockIdx.x;
+  const u64 b = wg_list ? (u64)wg_list[blockIdx.x] : wg0 + blockIdx.x;
   const int m = (int)P->m;
   u64 us, ue;
   if (part.balance_off) {
@@ -356,7 +411,8 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
   }
   if (threadIdx.x < 2 * MAXN) st.rng0[threadIdx.x] = rs.rng0[threadIdx.x];
   if (us >= ue) {
-    if (MODE == 0 && threadIdx.x == 0) counts[b] = 0;
+    if (MODE != 1 && threadIdx.x == 0) counts[b] = 0;
+    if (MODE == 2 && threadIdx.x == 0) P->ovf[b] = 0;
     return;
   }
   const u64 kfirst = owner_key(rs.C, 0, rs.K, us);
@@ -364,6 +420,8 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
   if (threadIdx.x == 0) {
     st.key_next = kfirst;
     st.out = 0;
+    st.covered = 0;
+    st.ovf = 0;
     for (int j = 0; j < MAXV; ++j) st.exam[j] = 0;
     st.exam[0] = klast - kfirst + 1;
     for (int j = 0; j < MAXV; ++j) st.n[j] = 0, st.total[j] = 0, st.cur[j] = 0;
@@ -404,15 +462,7 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
           }
         }
         if (m == 1) {
-          if (MODE == 0) {
-            my_count += alive ? 1 : 0;
-          } else {
-            u64 tot;
-            u64 rk = rank_alive(alive, st, &tot);
-            if (alive) emit_row(P, B, 0, 0, v, obase + st.out + rk);
-            __syncthreads();
-            if (threadIdx.x == 0) st.out += tot;
-          }
+          emit_chunk<MODE>(P, B, st, 0, 0, v, alive, obase, b, my_count);
         } else {
           u64 tot;
           u64 rk = rank_alive(alive, st, &tot);
@@ -440,7 +490,7 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
 
     if (L == m - 1) {
       // Leaf level: every surviving candidate is an output row.
-      if (MODE == 0 && P->leaf_fast) {
+      if (MODE == 0 && P->leaf_fast) {  // every candidate is a row: just add
         if (threadIdx.x == 0) my_count += st.total[bl] - st.cur[bl];
         __syncthreads();
         if (threadIdx.x == 0) st.cur[bl] = st.total[bl];
@@ -467,16 +517,7 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
           v = P->lvl[L].src[drv].col[r];
           alive = try_candidate(P, B, L, i, v, drv, r, NONE, slo, shi);
         }
-        if (MODE == 0) {
-          my_count += alive ? 1 : 0;
-        } else {
-          u64 tot;
-          u64 rk = rank_alive(alive, st, &tot);
-          if (alive) emit_row(P, B, L, i, v, obase + st.out + rk);
-          __syncthreads();
-          if (threadIdx.x == 0) st.out += tot;
-          __syncthreads();
-        }
+        emit_chunk<MODE>(P, B, st, L, i, v, alive, obase, b, my_count);
       }
       if (threadIdx.x == 0) st.cur[bl] = total;
       __syncthreads();
@@ -524,9 +565,36 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
     u64 tot;
     block_excl_scan(my_count, st.sh, &tot);
     if (threadIdx.x == 0) counts[b] = tot;
-  } else if (P->cand && threadIdx.x < P->m) {
+  } else if (MODE == 2) {
+    if (threadIdx.x == 0) {
+      counts[b] = st.out;
+      P->ovf[b] = st.ovf;
+    }
+  }
+  if (MODE != 0 && P->cand && threadIdx.x < P->m)
     atomicAdd(reinterpret_cast<unsigned long long*>(P->cand + threadIdx.x),
               (unsigned long long)st.exam[threadIdx.x]);
+}
+
+// Write pass for staged rows (one workgroup per arena chunk).
+__global__ __launch_bounds__(WG) void k_stage_copy(const DPlan* __restrict__ P, const u64* counts,
+                                                   const u64* offsets, u32 arity) {
+  const u64 c = blockIdx.x;
+  const u64 tag = P->chunk_tag[c];
+  const u64 b = tag >> 32, seq = tag & 0xffffffffull;
+  if (P->ovf[b]) return;  // re-run by the materialize pass
+  const u64 n = counts[b], start = seq * STAGE_CHUNK;
+  if (start >= n) return;
+  const u64 rows = n - start < STAGE_CHUNK ? n - start : STAGE_CHUNK;
+  const u64 dst = offsets[b] + start;
+  if (dst + rows > P->out_rows) {
+    if (threadIdx.x == 0) atomicOr(P->err, 1u);
+    return;
+  }
+  for (u32 h = 0; h < arity; ++h) {
+    const u32* src = P->stage[h] + c * STAGE_CHUNK;
+    u32* out = P->out[h] + dst;
+    for (u64 t = threadIdx.x; t < rows; t += WG) out[t] = src[t];
   }
 }
 
@@ -717,7 +785,8 @@ void join_histogram(Ctx c, const DPlan* d_plan, const RootSpace& rs, u64* W, u32
 }
 
 void join_run(Ctx c, const DPlan* d_plan, const RootSpace& rs, const Partition& part,
-              u32 lds_bytes, int mode, u64* counts, const u64* offsets, u64 wg0, u64 nwg) {
+              u32 lds_bytes, int mode, u64* counts, const u64* offsets, u64 wg0, u64 nwg,
+              const u32* wg_list) {
   if (nwg == 0) return;
   if (nwg > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "too many workgroups");
   if (lds_bytes > 60 * 1024) {
@@ -726,11 +795,23 @@ void join_run(Ctx c, const DPlan* d_plan, const RootSpace& rs, const Partition& 
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
     WCDL_HIP(hipFuncSetAttribute((const void*)k_join<1>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+    WCDL_HIP(hipFuncSetAttribute((const void*)k_join<2>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
   }
   if (mode == 0)
-    k_join<0><<<(u32)nwg, WG, lds_bytes, c.s>>>(d_plan, rs, part, counts, offsets, wg0);
+    k_join<0><<<(u32)nwg, WG, lds_bytes, c.s>>>(d_plan, rs, part, counts, offsets, wg0, wg_list);
+  else if (mode == 1)
+    k_join<1><<<(u32)nwg, WG, lds_bytes, c.s>>>(d_plan, rs, part, counts, offsets, wg0, wg_list);
   else
-    k_join<1><<<(u32)nwg, WG, lds_bytes, c.s>>>(d_plan, rs, part, counts, offsets, wg0);
+    k_join<2><<<(u32)nwg, WG, lds_bytes, c.s>>>(d_plan, rs, part, counts, offsets, wg0, wg_list);
+  WCDL_HIP(hipGetLastError());
+}
+
+void join_stage_copy(Ctx c, const DPlan* d_plan, u64 used_chunks, const u64* counts,
+                     const u64* offsets, u32 arity) {
+  if (used_chunks == 0) return;
+  if (used_chunks > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "too many staged chunks");
+  k_stage_copy<<<(u32)used_chunks, WG, 0, c.s>>>(d_plan, counts, offsets, arity);
   WCDL_HIP(hipGetLastError());
 }
 

@@ -27,6 +27,7 @@ LIB_PATH = os.path.join(HERE, "libwcdl.so")
 WCDL_F_BALANCE_OFF = 0x1
 WCDL_F_STREAMS_OFF = 0x2
 WCDL_F_XPROD_OFF = 0x4
+WCDL_F_STAGE_OFF = 0x8
 PHASES = ["histogram", "count", "materialize", "delta", "index", "merge", "load", "other"]
 KERNELS = ["join_count", "join_materialize", "join_histogram", "unused"]
 ERRORS = {-1: "E_INVALID", -2: "E_ARITY", -3: "E_UNKNOWN_REL", -4: "E_UNSAFE_RULE",
@@ -45,7 +46,7 @@ class _Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("n_streams", ctypes.c_uint32),
                 ("streams", ctypes.POINTER(ctypes.c_void_p)), ("alloc", _Allocator),
                 ("mem_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("wg_per_cu", ctypes.c_uint32)]
+                ("wg_per_cu", ctypes.c_uint32), ("stage_pct", ctypes.c_uint32)]
 
 
 class _Stats(ctypes.Structure):
@@ -137,7 +138,7 @@ class Engine:
     """One engine (one program over one set of relations) on one GPU."""
 
     def __init__(self, device: int = 0, streams=None, flags: int = 0, mem_budget: int = 0,
-                 wg_per_cu: int = 0, torch_alloc: bool = True):
+                 wg_per_cu: int = 0, stage_pct: int = 0, torch_alloc: bool = True):
         import torch  # device memory and streams come from PyTorch
 
         self._torch = torch
@@ -150,6 +151,7 @@ class Engine:
         cfg.flags = flags
         cfg.mem_budget_bytes = mem_budget
         cfg.wg_per_cu = wg_per_cu
+        cfg.stage_pct = stage_pct
         self._keep = []
         if torch_alloc:
             dev = torch.device("cuda", device)

@@ -10,8 +10,8 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2604_20073_amd import (WCDL_F_BALANCE_OFF, WCDL_F_STREAMS_OFF, WCDL_F_XPROD_OFF,
-                                  Engine, WcdlError)
+from paper_2604_20073_amd import (WCDL_F_BALANCE_OFF, WCDL_F_STAGE_OFF, WCDL_F_STREAMS_OFF,
+                                  WCDL_F_XPROD_OFF, Engine, WcdlError)
 from paper_2604_20073_amd import workloads as W
 from tests.checkers import render
 from tests.test_oracle_pins import ANDERSEN, ARITY, C4, PROGRAMS, Q4, TC, TRI
@@ -120,6 +120,7 @@ def test_andersen_small():
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("flags", [WCDL_F_BALANCE_OFF, WCDL_F_STREAMS_OFF, WCDL_F_XPROD_OFF,
+                                   WCDL_F_STAGE_OFF,
                                    WCDL_F_BALANCE_OFF | WCDL_F_STREAMS_OFF | WCDL_F_XPROD_OFF])
 def test_flags_do_not_change_results(flags):
     edges = W.rmat_graph(10, 6000, 31)
@@ -238,4 +239,26 @@ def test_memory_budget_is_enforced():
     with pytest.raises(WcdlError) as ei:
         e.run()
     assert ei.value.code == -8
+    e.close()
+
+
+@pytest.mark.parametrize("stage_pct", [0, 3, 40])
+def test_staged_count_pass(stage_pct):
+    """Second and later runs stage rows during the count pass (the arena is
+    sized from the first run); with a small arena most workgroups overflow
+    and are recomputed by the write pass.  Results stay identical."""
+    edges = W.rmat_graph(12, 40000, 41)
+    rels = {"edge": 2, "path": 2, "tri": 3, "q": 4}
+    rules = TC + "\n" + TRI + "\n" + Q4
+    o, expect = oracle.evaluate(rels, rules, {"edge": edges})
+    e = Engine(stage_pct=stage_pct)
+    for n, k in rels.items():
+        e.declare(n, k)
+    e.add_rules(rules)
+    e.load("edge", edges)
+    for _ in range(3):
+        e.run()
+        for n in rels:
+            assert np.array_equal(e.read_numpy(n), expect[n]), n
+        assert e.delta_sizes("path") == o.delta_sizes("path")
     e.close()
