@@ -40,6 +40,27 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(kernel: str, scale: int, edges: int):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None if it was taken on other kernel source or another
+    workload."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_k_join_rmat20_tri_q4.md")
+    src = os.path.join(ROOT, "paper_2604_20073_amd", "csrc", "wcoj.hip")
+    if not (os.path.exists(path) and scale == 20 and edges == 1 << 24):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get("wcoj_hip_sha256_16") != digest or not kernel.startswith(rec.get("kernel", "?")):
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(edges: np.ndarray, target_s: float, threads: int) -> dict:
     """The CPU oracle on a bounded sample: the same two rules with the
     outermost atom restricted to the edges of a random sample of source
@@ -86,6 +107,11 @@ def main():
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="instead of the benchmark: load one unary relation of BYTES/4 "
+                         "distinct values and run an empty program, so the run copies "
+                         "exactly BYTES through the engine's plain copy kernel (k_copy); "
+                         "used to calibrate hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the engine on a single MI355X "
@@ -96,6 +122,20 @@ def main():
 
     from paper_2604_20073_amd import Engine
     from paper_2604_20073_amd import workloads as W
+
+    if args.copy_probe:
+        n = args.copy_probe // 4
+        e = Engine(device=0)
+        e.declare("probe", 1)
+        e.load("probe", torch.arange(n, dtype=torch.int32, device="cuda").reshape(-1, 1))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e.run()  # copies the relation's loaded facts into its working copy
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "rows": n,
+                          "ms": round((time.perf_counter() - t0) * 1e3, 3)}), flush=True)
+        e.close()
+        return
 
     log(f"generating R-MAT scale {args.scale}, {args.edges} edges")
     edges = W.rmat_graph(args.scale, args.edges, W.SEED_BASE + 1)
@@ -143,7 +183,8 @@ def main():
     alg_bytes = cand * 4 + written
     achieved = (alg_bytes / (kms / 1000.0)) / 1e9 if kms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": profiled_traffic(kname, args.scale, args.edges),
                 "kernel": kname, "avg_launch_ms": round(kms / max(launches, 1), 3),
                 "bytes_per_launch": int(alg_bytes / max(launches, 1))}
     phases = {k: round(sum(s["phase_ms"][k] for s in stats) / args.steps, 2)
