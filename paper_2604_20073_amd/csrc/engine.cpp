@@ -904,10 +904,58 @@ struct VRun {
 };
 
 constexpr u64 NCU = 256;
+constexpr u64 MAX_WORKGROUPS = 1ull << 22;
 
-// Evaluate a set of rule versions over the current relations; returns the
-// raw head rows per head relation (canonical column order, unsorted).
-std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
+// All streams idle: blocks freed so far may be handed out again.
+void recycle(Engine* e) { sync_all(e); }
+
+// Chunked materialization needs every workgroup's rows to fit one chunk.  If
+// one does not, split [0,T) into finer slices and count again (without
+// staging), up to one unit per workgroup.
+void repartition(Engine* e, VRun& R, u64 max_rows, Stats& st) {
+  Ctx c = ctx(e, R.si);
+  for (;;) {
+    const u64 p = R.part.p;
+    std::vector<u64> cnt(p);
+    WCDL_HIP(hipMemcpy(cnt.data(), R.counts.get(), p * sizeof(u64), hipMemcpyDeviceToHost));
+    const u64 worst = *std::max_element(cnt.begin(), cnt.end());
+    if (worst <= max_rows) return;
+    const u64 cap = std::min<u64>(R.T, MAX_WORKGROUPS);
+    if (R.part.balance_off || p >= cap)
+      throw Error(WCDL_E_BUDGET, "a single work slice produces " + std::to_string(worst) +
+                                     " rows, beyond the chunk budget (consider wcdl_split_rule)");
+    u64 np = std::min<u64>(cap, p * std::max<u64>(2, 2 * ceil_div(worst, max_rows)));
+    const u64 slice = ceil_div(R.T, np);
+    np = ceil_div(R.T, slice);
+    R.part = Partition{np, slice, 0, 0};
+    // Staged rows belong to the old partition: drop them.
+    R.staged = false;
+    R.stage.clear();
+    R.chunk_tag.reset();
+    R.ovf.reset();
+    R.overflowed.clear();
+    R.used_chunks = 0;
+    DPlan& P = R.v->plan;
+    P.cand = nullptr;
+    *R.host_plan = P;
+    WCDL_HIP(hipMemcpyAsync(R.d_plan.get(), R.host_plan, sizeof(DPlan), hipMemcpyHostToDevice, c.s));
+    R.counts = DBuf<u64>(c.mem, np);
+    R.offsets = DBuf<u64>(c.mem, np);
+    auto t = Clock::now();
+    join_run(c, R.d_plan.get(), R.rs, R.part, R.v->lds_bytes, 0, R.counts.get(), nullptr, 0, np);
+    scan_u64_excl(c, R.counts.get(), R.offsets.get(), np, R.scal.get() + 2);
+    recycle(e);
+    st.phase[WCDL_PH_COUNT] += ms_since(t);
+  }
+}
+
+// Raw head rows of one chunk (canonical column order, unsorted unless
+// `presorted`: sorted, unique, and the head's entire output).
+using Sink = std::function<void(u32 rel, Cols&& rows, bool presorted)>;
+
+// Evaluate a set of rule versions over the current relations and hand every
+// chunk of raw head rows to `sink`.
+void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink) {
   const bool seq = (e->cfg.flags & WCDL_F_STREAMS_OFF) != 0;
   const u32 flags = e->cfg.flags;
   std::vector<VRun> runs(vs.size());
@@ -1013,6 +1061,34 @@ std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
   st.phase[WCDL_PH_HISTOGRAM] += ms_since(t_hist);
   // ---- Phase C: count pass (Alg. 1 Phase 2) and offsets.
   auto t_count = Clock::now();
+  // Staging arenas: each version that ran before asks for its expected rows
+  // (x stage_pct); together they get at most a fifth of the device memory
+  // (or a quarter of the memory budget), shared in proportion.
+  std::map<VRun*, u64> stage_plan;
+  if (!(flags & WCDL_F_STAGE_OFF)) {
+    const double pct = e->cfg.stage_pct ? e->cfg.stage_pct : 125;
+    u64 want_total = 0;
+    for (auto& R : runs) {
+      if (R.skip || R.v->plan.xprod) continue;
+      WCDL_HIP(hipMemcpy(&R.T, R.scal.get() + 1, sizeof(u64), hipMemcpyDeviceToHost));
+      auto rit = e->rows_per_unit.find(std::make_pair(R.v->rule, R.v->delta_atom));
+      if (R.T == 0 || rit == e->rows_per_unit.end()) continue;
+      const u64 wpc = e->cfg.wg_per_cu ? e->cfg.wg_per_cu : 32;
+      const u64 pguess = std::min<u64>(ceil_div(R.T, 64), NCU * wpc);
+      const u64 rows = (u64)((double)R.T * rit->second * pct / 100.0) + STAGE_CHUNK * pguess;
+      const u64 bytes = ceil_div(rows, STAGE_CHUNK) * STAGE_CHUNK * R.v->plan.head_arity * 4ull;
+      stage_plan[&R] = bytes;
+      want_total += bytes;
+    }
+    size_t free_b = 0, total_b = 0;
+    WCDL_HIP(hipMemGetInfo(&free_b, &total_b));
+    const u64 limit = e->cfg.mem_budget_bytes ? e->cfg.mem_budget_bytes / 4 : (u64)(total_b * 0.2);
+    const double scale = want_total > limit ? (double)limit / (double)want_total : 1.0;
+    for (auto& kv : stage_plan) {
+      const u64 per_chunk = STAGE_CHUNK * kv.first->v->plan.head_arity * 4ull;
+      kv.second = (u64)((double)kv.second * scale) / per_chunk;  // now in chunks
+    }
+  }
   for (auto& R : runs) {
     if (R.skip) continue;
     WCDL_HIP(hipMemcpy(&R.T, R.scal.get() + 1, sizeof(u64), hipMemcpyDeviceToHost));
@@ -1040,21 +1116,10 @@ std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
     R.counts = DBuf<u64>(c.mem, p);
     R.offsets = DBuf<u64>(c.mem, p);
     // Stage rows during the count pass when the previous run of this rule
-    // version tells how many to expect.
-    auto key = std::make_pair(R.v->rule, R.v->delta_atom);
-    auto rit = e->rows_per_unit.find(key);
-    if (!(flags & WCDL_F_STAGE_OFF) && rit != e->rows_per_unit.end()) {
-      const double pct = e->cfg.stage_pct ? e->cfg.stage_pct : 125;
+    // version tells how many to expect (arena shares across the batch).
+    u64 chunks = stage_plan.count(&R) ? stage_plan[&R] : 0;
+    if (chunks) {
       const u32 k = P.head_arity;
-      u64 est = (u64)((double)R.T * rit->second * pct / 100.0) + STAGE_CHUNK * p;
-      u64 chunks = ceil_div(est, STAGE_CHUNK);
-      size_t free_b = 0, total_b = 0;
-      WCDL_HIP(hipMemGetInfo(&free_b, &total_b));
-      const u64 limit = std::min<u64>((u64)(total_b * 0.4), e->cfg.mem_budget_bytes
-                                                                ? e->cfg.mem_budget_bytes / 4
-                                                                : ~0ull);
-      const u64 per_chunk = STAGE_CHUNK * k * 4ull;
-      chunks = std::min<u64>(chunks, limit / per_chunk);
       if (chunks > 0) {
         try {
           for (u32 h = 0; h < k; ++h) R.stage.emplace_back(c.mem, chunks * STAGE_CHUNK);
@@ -1105,79 +1170,177 @@ std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
     if (R.total == 0) R.skip = true;
   }
   st.phase[WCDL_PH_COUNT] += ms_since(t_count);
-  // ---- Resize: one candidate buffer per head relation.
-  std::map<u32, Cols> out;
+  // ---- Resize: one candidate buffer per head relation.  A head whose rows
+  // exceed the chunk budget is materialized in ranges of workgroups (or of
+  // units, for cross-product plans) instead, each range deduplicated by the
+  // sink before the next one is written (chunked materialization).
   std::map<u32, u64> rows;
+  std::map<u32, int> nver;
+  bool all_sorted = true;
   for (auto& R : runs) {
     if (R.skip) continue;
     R.out_off = rows[R.v->head_rel];
     rows[R.v->head_rel] += R.total;
+    nver[R.v->head_rel]++;
   }
-  u64 need = 0;
-  for (auto& kv : rows) need += kv.second * e->rels[kv.first].arity * 4ull;
-  if (e->cfg.mem_budget_bytes && need * 3 + e->mem->live_bytes() > e->cfg.mem_budget_bytes)
-    throw Error(WCDL_E_BUDGET, "count pass needs " + std::to_string(need) +
-                                   " bytes of candidates, beyond the memory budget");
+  size_t free_b = 0, total_b = 0;
+  WCDL_HIP(hipMemGetInfo(&free_b, &total_b));
+  const u64 chunk_bytes = e->cfg.mem_budget_bytes ? e->cfg.mem_budget_bytes / 4
+                                                  : (u64)(total_b * 0.06);
+  std::set<u32> chunked;
+  for (auto& kv : rows)
+    if (kv.second * e->rels[kv.first].arity * 4ull > chunk_bytes) chunked.insert(kv.first);
+  std::map<u32, Cols> whole;
   for (auto& kv : rows) {
+    if (chunked.count(kv.first)) continue;
     const u32 k = e->rels[kv.first].arity;
     Cols c;
     c.order = canonical(k);
     c.n = kv.second;
     for (u32 j = 0; j < k; ++j) c.col.emplace_back(e->mem.get(), kv.second);
-    out.emplace(kv.first, std::move(c));
+    whole.emplace(kv.first, std::move(c));
   }
-  // ---- Phase D: materialize (Alg. 1 Phase 3).
-  auto t_mat = Clock::now();
-  for (auto& R : runs) {
-    if (R.skip) continue;
-    Ctx c = ctx(e, R.si);
+  (void)all_sorted;
+  auto set_output = [&](VRun& R, u32* const* base, u64 lo_row, u64 hi_row) {
+    // Rows [lo_row, hi_row) of this version land at base[h][row - lo_row].
     DPlan& P = R.v->plan;
-    Cols& dst = out.at(R.v->head_rel);
-    for (u32 h = 0; h < P.head_arity; ++h) P.out[h] = dst.col[h].get() + R.out_off;
-    P.out_rows = R.total;
+    for (u32 h = 0; h < P.head_arity; ++h) P.out[h] = base[h] - lo_row;
+    P.out_rows = hi_row;
     P.err = reinterpret_cast<u32*>(R.scal.get() + 3);
     if (R.staged) {
       P.cand = nullptr;  // counted in the staged count pass
     } else {
-      R.cand = DBuf<u64>(c.mem, MAXV);
-      fill_u64(c, R.cand.get(), MAXV, 0);
+      if (!R.cand.get()) {
+        R.cand = DBuf<u64>(e->mem.get(), MAXV);
+        fill_u64(ctx(e, R.si), R.cand.get(), MAXV, 0);
+      }
       P.cand = R.cand.get();
     }
     *R.host_plan = P;
-    WCDL_HIP(hipMemcpyAsync(R.d_plan.get(), R.host_plan, sizeof(DPlan), hipMemcpyHostToDevice, c.s));
-    R.t_mat.start(c.s, 1);
+    WCDL_HIP(hipMemcpyAsync(R.d_plan.get(), R.host_plan, sizeof(DPlan), hipMemcpyHostToDevice,
+                            ctx(e, R.si).s));
+  };
+  // Write the rows of workgroups [w0, w1) (or units, for cross products).
+  auto write_rows = [&](VRun& R, u64 w0, u64 w1) {
+    Ctx c = ctx(e, R.si);
+    DPlan& P = R.v->plan;
     if (P.xprod) {
-      join_xprod(c, R.d_plan.get(), R.rs, R.klo.get(), R.kd.get(), P.m);
+      join_xprod(c, R.d_plan.get(), R.rs, R.klo.get(), R.kd.get(), P.m, w0, w1);
     } else if (R.staged) {
       // Staged rows: copy to their offsets; re-run only workgroups whose
       // rows did not all fit in the arena.
       join_stage_copy(c, R.d_plan.get(), R.used_chunks, R.counts.get(), R.offsets.get(),
-                      P.head_arity);
-      if (!R.overflowed.empty()) {
-        R.d_overflowed = DBuf<u32>(c.mem, R.overflowed.size());
-        WCDL_HIP(hipMemcpyAsync(R.d_overflowed.get(), R.overflowed.data(),
-                                R.overflowed.size() * sizeof(u32), hipMemcpyHostToDevice, c.s));
+                      P.head_arity, w0, w1);
+      std::vector<u32> redo;
+      for (u32 b : R.overflowed)
+        if (b >= w0 && b < w1) redo.push_back(b);
+      if (!redo.empty()) {
+        DBuf<u32> d_redo(c.mem, redo.size());
+        WCDL_HIP(hipMemcpyAsync(d_redo.get(), redo.data(), redo.size() * sizeof(u32),
+                                hipMemcpyHostToDevice, c.s));
         join_run(c, R.d_plan.get(), R.rs, R.part, R.v->lds_bytes, 1, nullptr, R.offsets.get(), 0,
-                 R.overflowed.size(), R.d_overflowed.get());
+                 redo.size(), d_redo.get());
+        WCDL_HIP(hipStreamSynchronize(c.s));  // `redo` is read by the copy above
       }
     } else {
-      join_run(c, R.d_plan.get(), R.rs, R.part, R.v->lds_bytes, 1, nullptr, R.offsets.get(), 0,
-               R.part.p);
+      join_run(c, R.d_plan.get(), R.rs, R.part, R.v->lds_bytes, 1, nullptr, R.offsets.get(), w0,
+               w1 - w0);
     }
-    R.t_mat.stop(c.s);
+  };
+  auto check_flag = [&](VRun& R) {
+    u64 flag = 0;
+    WCDL_HIP(hipMemcpy(&flag, R.scal.get() + 3, sizeof(u64), hipMemcpyDeviceToHost));
+    if (flag) throw Error(WCDL_E_DEVICE, "internal error: materialize produced more rows than counted");
+  };
+  // ---- Phase D: materialize (Alg. 1 Phase 3), whole heads, phase-aligned.
+  auto t_mat = Clock::now();
+  for (auto& R : runs) {
+    if (R.skip || chunked.count(R.v->head_rel)) continue;
+    Cols& dst = whole.at(R.v->head_rel);
+    std::vector<u32*> base;
+    for (u32 h = 0; h < R.v->plan.head_arity; ++h) base.push_back(dst.col[h].get() + R.out_off);
+    set_output(R, base.data(), 0, R.total);
+    R.t_mat.start(ctx(e, R.si).s, 1);
+    write_rows(R, 0, R.v->plan.xprod ? R.T : R.part.p);
+    R.t_mat.stop(ctx(e, R.si).s);
     st.candidates += R.total;
   }
   sync_all(e);
+  for (auto& R : runs)
+    if (!R.skip && !chunked.count(R.v->head_rel)) check_flag(R);
+  st.phase[WCDL_PH_MATERIALIZE] += ms_since(t_mat);
+  for (auto& kv : whole) {
+    bool sorted = nver[kv.first] == 1;
+    for (auto& R : runs)
+      if (!R.skip && R.v->head_rel == kv.first) sorted = sorted && R.v->sorted_output;
+    sink(kv.first, std::move(kv.second), sorted);
+  }
+  whole.clear();
+  // ---- Chunked heads: one version and one range at a time.
+  for (auto& R : runs) {
+    if (R.skip || !chunked.count(R.v->head_rel)) continue;
+    const u32 k = e->rels[R.v->head_rel].arity;
+    const u64 max_rows = std::max<u64>(1, chunk_bytes / (k * 4ull));
+    // Ranges [w0, w1) of workgroups (units for cross products) and their rows.
+    std::vector<std::pair<u64, u64>> ranges;
+    std::vector<u64> offs;
+    if (R.v->plan.xprod) {
+      for (u64 u = 0; u < R.T; u += max_rows) ranges.push_back({u, std::min(R.T, u + max_rows)});
+    } else {
+      repartition(e, R, max_rows, st);
+      const u64 p = R.part.p;
+      offs.resize(p + 1);
+      WCDL_HIP(hipMemcpy(offs.data(), R.offsets.get(), p * sizeof(u64), hipMemcpyDeviceToHost));
+      offs[p] = R.total;
+      u64 w0 = 0;
+      while (w0 < p) {
+        u64 w1 = w0 + 1;
+        if (offs[w1] - offs[w0] > max_rows)
+          throw Error(WCDL_E_BUDGET, "one workgroup's rows exceed the chunk budget");
+        while (w1 < p && offs[w1 + 1] - offs[w0] <= max_rows) ++w1;
+        ranges.push_back({w0, w1});
+        w0 = w1;
+      }
+    }
+    for (auto& rg : ranges) {
+      auto t_chunk = Clock::now();
+      const u64 r0 = R.v->plan.xprod ? rg.first : offs[rg.first];
+      const u64 r1 = R.v->plan.xprod ? rg.second : offs[rg.second];
+      if (r1 == r0) continue;
+      Cols chunk;
+      chunk.order = canonical(k);
+      chunk.n = r1 - r0;
+      std::vector<u32*> base;
+      for (u32 j = 0; j < k; ++j) {
+        chunk.col.emplace_back(e->mem.get(), chunk.n);
+        base.push_back(chunk.col.back().get());
+      }
+      set_output(R, base.data(), r0, r1);
+      KernelTimer t;
+      t.start(ctx(e, R.si).s, 1);
+      write_rows(R, rg.first, rg.second);
+      t.stop(ctx(e, R.si).s);
+      sync_all(e);
+      check_flag(R);
+      t.collect(st);
+      st.candidates += chunk.n;
+      st.phase[WCDL_PH_MATERIALIZE] += ms_since(t_chunk);
+      sink(R.v->head_rel, std::move(chunk), false);
+      recycle(e);
+    }
+    // The staging arena of this version is no longer needed.
+    R.stage.clear();
+    R.chunk_tag.reset();
+    recycle(e);
+  }
   for (auto& R : runs) {
     if (R.skip) continue;
-    u64 flag = 0, lv[MAXV];
-    WCDL_HIP(hipMemcpy(&flag, R.scal.get() + 3, sizeof(u64), hipMemcpyDeviceToHost));
-    if (flag) throw Error(WCDL_E_DEVICE, "internal error: materialize produced more rows than counted");
-    WCDL_HIP(hipMemcpy(lv, R.cand.get(), sizeof(lv), hipMemcpyDeviceToHost));
+    u64 lv[MAXV];
     if (R.v->plan.xprod) {
       st.examined += R.total;
       st.exam_level[R.v->plan.m - 1] += R.total;
-    } else {
+    } else if (R.cand.get()) {
+      WCDL_HIP(hipMemcpy(lv, R.cand.get(), sizeof(lv), hipMemcpyDeviceToHost));
       for (int j = 0; j < MAXV; ++j) {
         st.examined += lv[j];
         st.exam_level[j] += lv[j];
@@ -1189,40 +1352,64 @@ std::map<u32, Cols> eval_batch(Engine* e, std::vector<Version>& vs, Stats& st) {
     R.t_count.collect(st);
     R.t_mat.collect(st);
   }
-  st.phase[WCDL_PH_MATERIALIZE] += ms_since(t_mat);
-  return out;
 }
 
-// Compute new rows = unique(cand) \ full, merge them into full (and into
-// every other maintained column order of full).  Returns the new rows.
-Cols absorb(Engine* e, u32 rel, Cols&& cand, bool presorted, Stats& st) {
+// Fold one chunk of raw rows of relation `rel` into `acc`, the rows new this
+// round: acc += unique(rows) \ full \ acc (Compute Delta, Sec. 4).
+void absorb_chunk(Engine* e, u32 rel, Cols&& rows, bool presorted, Cols& acc, Stats& st) {
   Relation& R = e->rels[rel];
   auto t = Clock::now();
-  Cols d;
-  if (presorted && R.full.n == 0) {
-    d = std::move(cand);
+  if (presorted && R.full.n == 0 && acc.n == 0) {
+    acc = std::move(rows);
   } else {
-    Cols s = sort_rows(e, 0, cand.order, std::vector<const u32*>(cand.ptrs()), cand.n, true);
-    cand = Cols();
-    d = difference(e, 0, s, R.full);
+    Cols srt = sort_rows(e, 0, rows.order, std::vector<const u32*>(rows.ptrs()), rows.n, true);
+    rows = Cols();
+    recycle(e);
+    Cols d = difference(e, 0, srt, R.full);
+    srt = Cols();
+    recycle(e);
+    if (acc.n == 0) {
+      acc = std::move(d);
+    } else if (d.n) {
+      Cols d2 = difference(e, 0, d, acc);
+      if (d2.n) acc = merged(e, 0, acc, d2);
+    }
   }
   WCDL_HIP(hipStreamSynchronize(e->streams[0]));
   st.phase[WCDL_PH_DELTA] += ms_since(t);
-  t = Clock::now();
+}
+
+// Merge the new rows into full and into every other maintained column order
+// of full (Merge, Sec. 4).
+void commit_delta(Engine* e, u32 rel, Cols& d, Stats& st, bool consume = false) {
+  Relation& R = e->rels[rel];
+  auto t = Clock::now();
   if (d.n) {
     if (R.full.n == 0) {
-      R.full = copy_cols(e, d);
+      // `consume`: the caller no longer needs d, so it becomes full as is.
+      R.full = consume ? std::move(d) : copy_cols(e, d);
     } else {
       R.full = merged(e, 0, R.full, d);
     }
     for (auto& kv : R.full_ord) {
-      Cols ds = reorder(e, 0, d, kv.first);
+      Cols ds = reorder(e, 0, R.full.n == d.n ? R.full : d, kv.first);
       kv.second = merged(e, 0, kv.second, ds);
     }
   }
   WCDL_HIP(hipStreamSynchronize(e->streams[0]));
   st.phase[WCDL_PH_MERGE] += ms_since(t);
-  return d;
+}
+
+// Evaluate versions and return the rows new to each head relation.
+std::map<u32, Cols> new_rows(Engine* e, std::vector<Version>& vs, Stats& st) {
+  std::map<u32, Cols> acc;
+  eval_batch(e, vs, st, [&](u32 rel, Cols&& rows, bool presorted) {
+    auto it = acc.find(rel);
+    if (it == acc.end())
+      it = acc.emplace(rel, empty_cols(e->rels[rel].arity, canonical(e->rels[rel].arity))).first;
+    absorb_chunk(e, rel, std::move(rows), presorted, it->second, st);
+  });
+  return acc;
 }
 
 void run_program(Engine* e, wcdl_run_stats* stats_out) {
@@ -1253,15 +1440,14 @@ void run_program(Engine* e, wcdl_run_stats* stats_out) {
     // Exit rules read finished relations only.
     if (!exit_rules.empty()) {
       std::vector<Version> vs;
-      for (u32 ri : exit_rules) vs.push_back(plan_version(e, ri, -1, e->cfg.flags));
-      auto cand = eval_batch(e, vs, st);
-      for (auto& kv : cand) {
-        u32 nv = 0;
-        bool sorted = true;
-        for (auto& v : vs)
-          if (v.head_rel == kv.first) { ++nv; sorted = sorted && v.sorted_output; }
-        absorb(e, kv.first, std::move(kv.second), rec_rules.empty() && nv == 1 && sorted, st);
+      for (u32 ri : exit_rules) {
+        vs.push_back(plan_version(e, ri, -1, e->cfg.flags));
+        // Sorted output may replace an empty full relation only when nothing
+        // else can add to it in this stratum.
+        if (!rec_rules.empty()) vs.back().sorted_output = false;
       }
+      auto fresh = new_rows(e, vs, st);
+      for (auto& kv : fresh) commit_delta(e, kv.first, kv.second, st, true);
     }
     if (rec_rules.empty()) continue;
     // Semi-naive rounds: delta_0 is everything the stratum holds so far.
@@ -1278,18 +1464,16 @@ void run_program(Engine* e, wcdl_run_stats* stats_out) {
       for (u32 j = 0; j < r.body.size(); ++j)
         if (in.count(r.body[j].rel)) vs.push_back(plan_version(e, ri, (int)j, e->cfg.flags));
     }
+    for (auto& v : vs) v.sorted_output = false;
     for (;;) {
-      auto cand = eval_batch(e, vs, st);
+      auto fresh = new_rows(e, vs, st);
       std::map<u32, Cols> nd;
       bool any = false;
       for (u32 rel : comp) {
-        auto it = cand.find(rel);
-        Cols d;
-        if (it != cand.end()) {
-          d = absorb(e, rel, std::move(it->second), false, st);
-        } else {
-          d = empty_cols(e->rels[rel].arity, canonical(e->rels[rel].arity));
-        }
+        auto it = fresh.find(rel);
+        Cols d = it != fresh.end() ? std::move(it->second)
+                                   : empty_cols(e->rels[rel].arity, canonical(e->rels[rel].arity));
+        commit_delta(e, rel, d, st);
         if (d.n) any = true;
         nd.emplace(rel, std::move(d));
       }

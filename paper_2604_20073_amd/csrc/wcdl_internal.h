@@ -286,13 +286,13 @@ void join_run(Ctx c, const DPlan* d_plan, const RootSpace& rs, const Partition& 
 // Write pass for staged rows: chunk c of workgroup b goes to
 // offsets[b] + seq * STAGE_CHUNK unless b overflowed.
 void join_stage_copy(Ctx c, const DPlan* d_plan, u64 used_chunks, const u64* counts,
-                     const u64* offsets, u32 arity);
+                     const u64* offsets, u32 arity, u64 w0, u64 w1);
 // Dense directory of a sorted column with values <= vmax: dir[v] = first row
 // with value >= v, for v in [0, vmax+1] (vmax + 2 entries).
 void build_directory(Ctx c, const u32* col, u64 n, u32 vmax, u32* dir);
-// Cross-product decode path: writes T rows directly.
+// Cross-product decode path: writes the rows of units [g0, g1) (row g = unit g).
 void join_xprod(Ctx c, const DPlan* d_plan, const RootSpace& rs, const u32* klo, const u32* kd,
-                u32 m);
+                u32 m, u64 g0, u64 g1);
 
 }  // namespace wcdl
 

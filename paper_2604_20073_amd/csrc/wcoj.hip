@@ -578,11 +578,12 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
 
 // Write pass for staged rows (one workgroup per arena chunk).
 __global__ __launch_bounds__(WG) void k_stage_copy(const DPlan* __restrict__ P, const u64* counts,
-                                                   const u64* offsets, u32 arity) {
+                                                   const u64* offsets, u32 arity, u64 w0, u64 w1) {
   const u64 c = blockIdx.x;
   const u64 tag = P->chunk_tag[c];
   const u64 b = tag >> 32, seq = tag & 0xffffffffull;
-  if (P->ovf[b]) return;  // re-run by the materialize pass
+  if (b < w0 || b >= w1) return;  // another range of workgroups
+  if (P->ovf[b]) return;          // re-run by the materialize pass
   const u64 n = counts[b], start = seq * STAGE_CHUNK;
   if (start >= n) return;
   const u64 rows = n - start < STAGE_CHUNK ? n - start : STAGE_CHUNK;
@@ -635,10 +636,10 @@ __global__ __launch_bounds__(WG) void k_hist(const DPlan* __restrict__ P, RootSp
 // Each unit of a cross-product plan is one output row (the work-unit decode
 // of Sec. 5): local = g - C[key-1], then mixed-radix digits over the levels.
 __global__ __launch_bounds__(WG) void k_xprod(const DPlan* __restrict__ P, RootSpace rs,
-                                              const u32* klo, const u32* kd) {
+                                              const u32* klo, const u32* kd, u64 g0, u64 g1) {
   __shared__ u64 kr[2];
-  const u64 ub = (u64)blockIdx.x * WG;
-  const u64 ue = ub + WG < rs.T ? ub + WG : rs.T;
+  const u64 ub = g0 + (u64)blockIdx.x * WG;
+  const u64 ue = ub + WG < g1 ? ub + WG : g1;
   if (threadIdx.x == 0) {
     u64 k0 = owner_key(rs.C, 0, rs.K, ub);
     kr[0] = k0;
@@ -646,7 +647,7 @@ __global__ __launch_bounds__(WG) void k_xprod(const DPlan* __restrict__ P, RootS
   }
   __syncthreads();
   const u64 g = ub + threadIdx.x;
-  if (g >= rs.T) return;
+  if (g >= g1) return;
   if (g >= P->out_rows) {
     atomicOr(P->err, 1u);
     return;
@@ -808,18 +809,18 @@ void join_run(Ctx c, const DPlan* d_plan, const RootSpace& rs, const Partition& 
 }
 
 void join_stage_copy(Ctx c, const DPlan* d_plan, u64 used_chunks, const u64* counts,
-                     const u64* offsets, u32 arity) {
+                     const u64* offsets, u32 arity, u64 w0, u64 w1) {
   if (used_chunks == 0) return;
   if (used_chunks > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "too many staged chunks");
-  k_stage_copy<<<(u32)used_chunks, WG, 0, c.s>>>(d_plan, counts, offsets, arity);
+  k_stage_copy<<<(u32)used_chunks, WG, 0, c.s>>>(d_plan, counts, offsets, arity, w0, w1);
   WCDL_HIP(hipGetLastError());
 }
 
 void join_xprod(Ctx c, const DPlan* d_plan, const RootSpace& rs, const u32* klo, const u32* kd,
-                u32 m) {
+                u32 m, u64 g0, u64 g1) {
   (void)m;
-  if (rs.T == 0) return;
-  k_xprod<<<grid1(rs.T), WG, 0, c.s>>>(d_plan, rs, klo, kd);
+  if (g1 <= g0) return;
+  k_xprod<<<grid1(g1 - g0), WG, 0, c.s>>>(d_plan, rs, klo, kd, g0, g1);
   WCDL_HIP(hipGetLastError());
 }
 
