@@ -72,6 +72,17 @@ typedef int32_t wcdl_status;
                                     decode); use the general kernel instead */
 #define WCDL_F_STAGE_OFF 0x8u    /* never stage rows during the count pass: the
                                     write pass always re-runs the traversal */
+#define WCDL_F_BATCHED 0x10u     /* batched mode: the engine holds many independent
+                                    instances of one program.  Every relation gets
+                                    an implicit leading column, the instance id:
+                                    wcdl_load_columns / wcdl_read_columns take and
+                                    return arity + 1 columns, column 0 holding the
+                                    instance id, and every rule is evaluated within
+                                    each instance (an instance variable is added to
+                                    its head and to every body atom).  One run
+                                    evaluates all instances together.  Declared
+                                    arities are then limited to WCDL_MAX_ARITY - 1
+                                    and rules to WCDL_MAX_VARS - 1 variables. */
 
 typedef struct wcdl_engine wcdl_engine;
 
@@ -261,6 +272,26 @@ wcdl_status wcdl_relation_size(const wcdl_engine* e, uint32_t rel, uint64_t* n_r
  * (min(size, capacity)); use wcdl_relation_size first. */
 wcdl_status wcdl_read_columns(const wcdl_engine* e, uint32_t rel, uint32_t* const* cols_out,
                               uint64_t capacity, uint64_t* n_written, int on_device);
+
+/* Rows of a relation whose column 0 equals `lead` (in batched mode: the rows
+ * of one instance): they are the contiguous rows [*first, *first + *count)
+ * of the sorted relation. */
+wcdl_status wcdl_relation_range(const wcdl_engine* e, uint32_t rel, uint32_t lead,
+                                uint64_t* first, uint64_t* count);
+
+/* Copy rows [first, first + n) of the sorted relation (all stored columns,
+ * the instance column included in batched mode) into cols_out[j] (n values
+ * each; device or host pointers as on_device says).  Fails with
+ * WCDL_E_INVALID if the range exceeds the relation. */
+wcdl_status wcdl_read_rows(const wcdl_engine* e, uint32_t rel, uint64_t first, uint64_t n,
+                           uint32_t* const* cols_out, int on_device);
+
+/* Autotuner: run the program once per candidate work-partition granularity
+ * (workgroups per CU, see wcdl_config.wg_per_cu), keep the fastest for later
+ * runs and report it in *chosen (and its run time in *best_ms).  The relations
+ * hold the last candidate's (identical) results afterwards. */
+wcdl_status wcdl_autotune(wcdl_engine* e, const uint32_t* wg_per_cu, uint32_t n, uint32_t* chosen,
+                          double* best_ms);
 
 /* Sizes of a relation's per-round deltas in its (recursive) stratum during
  * the last run: |delta_0|, |delta_1|, ..., ending with the empty one.

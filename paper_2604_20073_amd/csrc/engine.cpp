@@ -134,7 +134,8 @@ struct Rule {
 
 struct Relation {
   std::string name;
-  u32 arity = 0;
+  u32 arity = 0;        // stored columns (the instance column included in batched mode)
+  u32 user_arity = 0;   // columns as declared
   Cols base;                                   // loaded facts, canonical order
   Cols full;                                   // current relation, canonical order
   std::map<std::vector<u32>, Cols> full_ord;   // other column orders of full
@@ -1512,6 +1513,17 @@ void run_program(Engine* e, wcdl_run_stats* stats_out) {
 // Rule construction and validation
 // ===========================================================================
 
+bool batched(const Engine* e) { return (e->cfg.flags & WCDL_F_BATCHED) != 0; }
+
+// Batched mode: thread an instance variable through the head and every body
+// atom, so each rule only ever combines facts of one instance.
+void batch_rewrite(Rule& r) {
+  const u32 inst = r.nvars++;
+  r.head.t.insert(r.head.t.begin(), Term{true, inst});
+  for (auto& a : r.body) a.t.insert(a.t.begin(), Term{true, inst});
+  if (!r.var_order.empty()) r.var_order.insert(r.var_order.begin(), inst);
+}
+
 void validate_rule(Engine* e, const Rule& r) {
   auto check_atom = [&](const Atom& a) {
     if (a.rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
@@ -1630,13 +1642,14 @@ void parse_rules(Engine* e, const std::string& text, std::vector<Rule>& rules,
           if (!lx.lit(",")) lx.fail("expected ',' or ')'");
         }
       }
-      if (a.t.size() != e->rels[a.rel].arity)
+      if (a.t.size() != e->rels[a.rel].user_arity)
         throw Error(WCDL_E_ARITY, "wrong number of arguments for " + name);
     };
     std::string name;
     if (!lx.ident(name)) lx.fail("expected a relation name");
     atom_args(r.head, name);
     if (lx.lit(".")) {
+      if (batched(e)) throw Error(WCDL_E_UNSUPPORTED, "facts in rule text need an instance in batched mode");
       std::vector<u32> row;
       for (auto& t : r.head.t) {
         if (t.var) throw Error(WCDL_E_UNSAFE_RULE, "a fact must be ground");
@@ -1673,6 +1686,7 @@ void parse_rules(Engine* e, const std::string& text, std::vector<Rule>& rules,
       if (lx.lit(".")) break;
       if (!lx.lit(",")) lx.fail("expected ',' or '.'");
     }
+    if (batched(e)) batch_rewrite(r);
     validate_rule(e, r);
     rules.push_back(r);
   }
@@ -1720,12 +1734,17 @@ bool valid_name(const char* s) {
   return true;
 }
 
-u32 declare(Engine* e, const std::string& name, u32 arity) {
+u32 declare(Engine* e, const std::string& name, u32 arity, bool internal = false) {
+  // `internal`: arity already counts the instance column (helper relations).
   if (!valid_name(name.c_str())) throw Error(WCDL_E_INVALID, "bad relation name");
-  if (arity == 0 || arity > (u32)MAXA) throw Error(WCDL_E_UNSUPPORTED, "arity must be 1..6");
+  const u32 extra = (batched(e) && !internal) ? 1 : 0;
+  if (arity == 0 || arity + extra > (u32)MAXA)
+    throw Error(WCDL_E_UNSUPPORTED, extra ? "arity must be 1..5 in batched mode" : "arity must be 1..6");
   if (e->rel_ids.count(name)) throw Error(WCDL_E_INVALID, "relation " + name + " already declared");
   Relation R;
   R.name = name;
+  R.user_arity = internal && batched(e) ? arity - 1 : arity;
+  arity += extra;
   R.arity = arity;
   R.base = empty_cols(arity, canonical(arity));
   R.full = empty_cols(arity, canonical(arity));
@@ -1849,6 +1868,13 @@ wcdl_status wcdl_add_rule(wcdl_engine* e, const wcdl_rule* rule, uint32_t* rule_
   return guarded(e, [&] {
     if (!rule) throw Error(WCDL_E_INVALID, "null rule");
     Rule r = from_c(rule);
+    for (auto* a : {&r.head})
+      if (a->rel < e->rels.size() && a->t.size() != e->rels[a->rel].user_arity)
+        throw Error(WCDL_E_ARITY, "head arity differs from the declaration");
+    for (auto& a : r.body)
+      if (a.rel < e->rels.size() && a.t.size() != e->rels[a.rel].user_arity)
+        throw Error(WCDL_E_ARITY, "atom arity differs from the declaration");
+    if (batched(e)) batch_rewrite(r);
     validate_rule(e, r);
     e->rules.push_back(r);
     if (rule_id) *rule_id = (u32)e->rules.size() - 1;
@@ -1945,7 +1971,7 @@ wcdl_status wcdl_split_rule(wcdl_engine* e, uint32_t rule_id, const uint32_t* at
       if (!sel.count(a)) consumer.body.push_back(r.body[a]);
     consumer.body.push_back(helper.head);
     consumer.cmps = rest_cmps;
-    declare(e, hname, (u32)shared.size());
+    declare(e, hname, (u32)shared.size(), true);
     try {
       validate_rule(e, helper);
       validate_rule(e, consumer);
@@ -2003,6 +2029,66 @@ wcdl_status wcdl_delta_sizes(const wcdl_engine* ce, uint32_t rel, uint64_t* out,
     const auto& d = e->rels[rel].delta_sizes;
     for (u64 i = 0; i < d.size() && i < cap && out; ++i) out[i] = d[i];
     if (count) *count = d.size();
+  });
+}
+
+wcdl_status wcdl_relation_range(const wcdl_engine* ce, uint32_t rel, uint32_t lead,
+                                uint64_t* first, uint64_t* count) {
+  auto* e = const_cast<wcdl_engine*>(ce);
+  return guarded(e, [&] {
+    if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
+    const Relation& R = e->rels[rel];
+    const Cols& src = R.full.n ? R.full : R.base;
+    u64 lohi[2] = {0, 0};
+    if (src.n) {
+      DBuf<u64> d(e->mem.get(), 2);
+      lead_range(ctx(e), src.col[0].get(), src.n, lead, d.get());
+      WCDL_HIP(hipMemcpyAsync(lohi, d.get(), sizeof(lohi), hipMemcpyDeviceToHost, e->streams[0]));
+      WCDL_HIP(hipStreamSynchronize(e->streams[0]));
+    }
+    if (first) *first = lohi[0];
+    if (count) *count = lohi[1] - lohi[0];
+  });
+}
+
+wcdl_status wcdl_read_rows(const wcdl_engine* ce, uint32_t rel, uint64_t first, uint64_t n,
+                           uint32_t* const* cols_out, int on_device) {
+  auto* e = const_cast<wcdl_engine*>(ce);
+  return guarded(e, [&] {
+    if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
+    const Relation& R = e->rels[rel];
+    const Cols& src = R.full.n ? R.full : R.base;
+    if (first > src.n || n > src.n - first) throw Error(WCDL_E_INVALID, "row range out of bounds");
+    if (n && !cols_out) throw Error(WCDL_E_INVALID, "null output columns");
+    for (u32 j = 0; j < R.arity && n; ++j) {
+      if (!cols_out[j]) throw Error(WCDL_E_INVALID, "null output column");
+      WCDL_HIP(hipMemcpyAsync(cols_out[j], src.col[j].get() + first, n * sizeof(u32),
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                              e->streams[0]));
+    }
+    WCDL_HIP(hipStreamSynchronize(e->streams[0]));
+  });
+}
+
+wcdl_status wcdl_autotune(wcdl_engine* e, const uint32_t* wg_per_cu, uint32_t n, uint32_t* chosen,
+                          double* best_ms) {
+  return guarded(e, [&] {
+    if (!wg_per_cu || n == 0) throw Error(WCDL_E_INVALID, "no candidates");
+    u32 best = 0;
+    double bt = 0;
+    for (u32 i = 0; i < n; ++i) {
+      if (wg_per_cu[i] == 0) throw Error(WCDL_E_INVALID, "candidate must be positive");
+      e->cfg.wg_per_cu = wg_per_cu[i];
+      wcdl_run_stats s{};
+      run_program(e, &s);
+      if (i == 0 || s.wall_ms < bt) {
+        bt = s.wall_ms;
+        best = wg_per_cu[i];
+      }
+    }
+    e->cfg.wg_per_cu = best;
+    if (chosen) *chosen = best;
+    if (best_ms) *best_ms = bt;
   });
 }
 

@@ -390,10 +390,30 @@ __global__ __launch_bounds__(WG) void k_merge_place(ColsIn a, ColsIn b, ColsOut 
   }
 }
 
+__global__ void k_lead_range(const u32* col, u64 n, u32 v, u64* out) {
+  u64 lo = 0, hi = n;
+  while (lo < hi) {
+    u64 mid = lo + ((hi - lo) >> 1);
+    if (col[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  u64 lo2 = lo, hi2 = n;
+  while (lo2 < hi2) {
+    u64 mid = lo2 + ((hi2 - lo2) >> 1);
+    if (col[mid] <= v) lo2 = mid + 1; else hi2 = mid;
+  }
+  out[0] = lo;
+  out[1] = lo2;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Launchers
+
+void lead_range(Ctx c, const u32* col, u64 n, u32 v, u64* d_out) {
+  k_lead_range<<<1, 1, 0, c.s>>>(col, n, v, d_out);
+  WCDL_HIP(hipGetLastError());
+}
 // ---------------------------------------------------------------------------
 
 void scan_u32_excl(Ctx c, const u32* in, u64* out, u64 n, u64* d_total) {

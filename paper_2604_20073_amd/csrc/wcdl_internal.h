@@ -259,6 +259,8 @@ u64 set_difference(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* 
 // Merge two disjoint sorted-unique runs into out (na + nb rows).
 void merge_disjoint(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* b, u64 nb,
                     u32* const* out);
+// Rows of sorted column `col` equal to v: d_out[0] = first, d_out[1] = end.
+void lead_range(Ctx c, const u32* col, u64 n, u32 v, u64* d_out);
 // Fill helpers.
 void fill_u32(Ctx c, u32* p, u64 n, u32 v);
 void fill_u64(Ctx c, u64* p, u64 n, u64 v);

@@ -28,6 +28,7 @@ WCDL_F_BALANCE_OFF = 0x1
 WCDL_F_STREAMS_OFF = 0x2
 WCDL_F_XPROD_OFF = 0x4
 WCDL_F_STAGE_OFF = 0x8
+WCDL_F_BATCHED = 0x10
 PHASES = ["histogram", "count", "materialize", "delta", "index", "merge", "load", "other"]
 KERNELS = ["join_count", "join_materialize", "join_histogram", "unused"]
 ERRORS = {-1: "E_INVALID", -2: "E_ARITY", -3: "E_UNKNOWN_REL", -4: "E_UNSAFE_RULE",
@@ -71,7 +72,8 @@ EXPORTS = [
     "wcdl_declare_relation", "wcdl_relation_id", "wcdl_load_columns", "wcdl_clear_relation",
     "wcdl_add_rule", "wcdl_add_rules_text", "wcdl_rule_count", "wcdl_split_rule", "wcdl_run",
     "wcdl_relation_size", "wcdl_read_columns", "wcdl_delta_sizes", "wcdl_work_slice",
-    "wcdl_owner_key", "wcdl_decode_unit",
+    "wcdl_owner_key", "wcdl_decode_unit", "wcdl_relation_range", "wcdl_read_rows",
+    "wcdl_autotune",
 ]
 
 
@@ -101,6 +103,9 @@ def lib():
     L.wcdl_relation_size.argtypes = [P, u32, pu64]
     L.wcdl_read_columns.argtypes = [P, u32, ctypes.POINTER(P), u64, pu64, ctypes.c_int]
     L.wcdl_delta_sizes.argtypes = [P, u32, pu64, u64, pu64]
+    L.wcdl_relation_range.argtypes = [P, u32, u32, pu64, pu64]
+    L.wcdl_read_rows.argtypes = [P, u32, u64, u64, ctypes.POINTER(P), ctypes.c_int]
+    L.wcdl_autotune.argtypes = [P, pu32, u32, pu32, ctypes.POINTER(ctypes.c_double)]
     L.wcdl_work_slice.argtypes = [u64, u64, u64, pu64, pu64]
     L.wcdl_work_slice.restype = None
     L.wcdl_owner_key.argtypes = [pu64, u64, u64]
@@ -138,7 +143,8 @@ class Engine:
     """One engine (one program over one set of relations) on one GPU."""
 
     def __init__(self, device: int = 0, streams=None, flags: int = 0, mem_budget: int = 0,
-                 wg_per_cu: int = 0, stage_pct: int = 0, torch_alloc: bool = True):
+                 wg_per_cu: int = 0, stage_pct: int = 0, torch_alloc: bool = True,
+                 batched: bool = False):
         import torch  # device memory and streams come from PyTorch
 
         self._torch = torch
@@ -148,7 +154,8 @@ class Engine:
         cfg = _Config()
         self._lib.wcdl_config_default(ctypes.byref(cfg))
         cfg.device = device
-        cfg.flags = flags
+        cfg.flags = flags | (WCDL_F_BATCHED if batched else 0)
+        self.batched = batched
         cfg.mem_budget_bytes = mem_budget
         cfg.wg_per_cu = wg_per_cu
         cfg.stage_pct = stage_pct
@@ -209,7 +216,8 @@ class Engine:
     def declare(self, name: str, arity: int) -> int:
         rid = ctypes.c_uint32()
         self._check(self._lib.wcdl_declare_relation(self._e, name.encode(), arity, ctypes.byref(rid)))
-        self.arity[name] = arity
+        # Stored columns: batched engines keep the instance id in column 0.
+        self.arity[name] = arity + (1 if self.batched else 0)
         self.ids[name] = rid.value
         return rid.value
 
@@ -297,6 +305,35 @@ class Engine:
         w = ctypes.c_uint64()
         self._check(self._lib.wcdl_read_columns(self._e, self.ids[name], arr, n, ctypes.byref(w), 0))
         return np.ascontiguousarray(out[:, :n].T)
+
+    def range(self, name: str, lead: int):
+        """(first, count): the rows whose column 0 equals `lead` (in a
+        batched engine: the rows of instance `lead`)."""
+        f, c = ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self._lib.wcdl_relation_range(self._e, self.ids[name], lead, ctypes.byref(f),
+                                                  ctypes.byref(c)))
+        return f.value, c.value
+
+    def read_rows_numpy(self, name: str, first: int, n: int) -> np.ndarray:
+        """Rows [first, first+n) of the sorted relation, all stored columns."""
+        k = self.arity[name]
+        out = np.empty((k, max(n, 1)), dtype=np.uint32)
+        arr = (ctypes.c_void_p * k)(*[out[j].ctypes.data for j in range(k)])
+        self._check(self._lib.wcdl_read_rows(self._e, self.ids[name], first, n, arr, 0))
+        return np.ascontiguousarray(out[:, :n].T)
+
+    def read_instance(self, name: str, instance: int) -> np.ndarray:
+        """Batched engine: one instance's rows (instance column dropped)."""
+        first, n = self.range(name, instance)
+        return np.ascontiguousarray(self.read_rows_numpy(name, first, n)[:, 1:])
+
+    def autotune(self, wg_per_cu=(4, 8, 16, 32, 64)):
+        """Run the program once per partition granularity, keep the fastest."""
+        c = (ctypes.c_uint32 * len(wg_per_cu))(*wg_per_cu)
+        chosen, ms = ctypes.c_uint32(), ctypes.c_double()
+        self._check(self._lib.wcdl_autotune(self._e, c, len(wg_per_cu), ctypes.byref(chosen),
+                                            ctypes.byref(ms)))
+        return chosen.value, ms.value
 
     def delta_sizes(self, name: str) -> list:
         cnt = ctypes.c_uint64()

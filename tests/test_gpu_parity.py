@@ -306,3 +306,67 @@ def test_andersen_full_size_by_module():
         assert np.array_equal(mine, expect["pt"]), k
     assert stats["rounds"] > 5
     e.close()
+
+
+# --------------------------------------------------------------------------
+# Batched mode: many instances of one program in one run.
+# --------------------------------------------------------------------------
+
+def batch_facts(graphs):
+    """Stack instances' edges with their instance id in column 0."""
+    return np.concatenate([np.concatenate([np.full((len(g), 1), i, np.uint32), g], axis=1)
+                           for i, g in enumerate(graphs)]).astype(np.uint32)
+
+
+def test_batched_instances_match_alone():
+    sizes = W.batch_sizes(60, 77, lo=5, hi=300)
+    graphs = [W.batch_instance(W.SEED_BASE + 3, i, int(n)) for i, n in enumerate(sizes)]
+    rules = TC + "\n" + TRI
+    e = Engine(batched=True)
+    for n, k in {"edge": 2, "path": 2, "tri": 3}.items():
+        e.declare(n, k)
+    e.add_rules(rules)
+    e.load("edge", batch_facts(graphs))
+    stats = e.run()
+    total = 0
+    for i, g in enumerate(graphs):
+        _, expect = oracle.evaluate({"edge": 2, "path": 2, "tri": 3}, rules, {"edge": g})
+        for n in ("path", "tri"):
+            got = e.read_instance(n, i)
+            assert np.array_equal(got, expect[n]), (i, n)
+            total += len(got)
+    assert stats["derived_rows"] == total
+    e.close()
+
+
+def test_batched_rejects_bad_arity_and_keeps_comparisons():
+    e = Engine(batched=True)
+    e.declare("edge", 2)
+    e.declare("lt", 2)
+    e.add_rules("lt(x, y) :- edge(x, y), x < y.")
+    with pytest.raises(WcdlError):
+        e.declare("wide", 6)  # 5 columns at most next to the instance id
+    g0 = np.array([[1, 2], [3, 1]], np.uint32)
+    g1 = np.array([[5, 4], [0, 7]], np.uint32)
+    e.load("edge", batch_facts([g0, g1]))
+    e.run()
+    assert e.read_instance("lt", 0).tolist() == [[1, 2]]
+    assert e.read_instance("lt", 1).tolist() == [[0, 7]]
+    e.close()
+
+
+def test_autotune_keeps_results():
+    edges = W.rmat_graph(11, 15000, 13)
+    rules = TRI + "\n" + Q4
+    _, expect = oracle.evaluate({"edge": 2, "tri": 3, "q": 4}, rules, {"edge": edges})
+    e = Engine()
+    for n, k in {"edge": 2, "tri": 3, "q": 4}.items():
+        e.declare(n, k)
+    e.add_rules(rules)
+    e.load("edge", edges)
+    chosen, ms = e.autotune((2, 8, 32))
+    assert chosen in (2, 8, 32) and ms > 0
+    e.run()
+    for n in ("tri", "q"):
+        assert np.array_equal(e.read_numpy(n), expect[n])
+    e.close()
