@@ -293,6 +293,48 @@ wcdl_status wcdl_read_rows(const wcdl_engine* e, uint32_t rel, uint64_t first, u
 wcdl_status wcdl_autotune(wcdl_engine* e, const uint32_t* wg_per_cu, uint32_t n, uint32_t* chosen,
                           double* best_ms);
 
+/* ---- Continuous evaluation (serving), batched engines only -------------
+ *
+ * A positive program's least model is also reached by one semi-naive loop
+ * over all rules in which every relation, input relations included, has a
+ * delta (Sec. 2's differential form; stratification is only an evaluation
+ * order for positive programs).  Serving runs that loop one round per
+ * wcdl_serve_step; facts admitted between steps are the next round's delta of
+ * their relations, so new instances join while others are in flight and
+ * share every launch with them (Sec. 6's monotonicity argument: the order in
+ * which facts arrive does not change any instance's least model). */
+
+typedef struct {
+  uint64_t candidate_rows;  /* rows counted by this step's count passes: the
+                               memory bound of the step (x arity x 4 bytes) */
+  uint64_t new_rows;        /* rows new to the relations after this step */
+  uint64_t resident_rows;   /* rows held by all relations after this step */
+  double wall_ms;
+} wcdl_step_stats;
+
+/* Start serving: relations keep their loaded facts, derived relations are
+ * reset to them, every delta is empty.  Requires WCDL_F_BATCHED. */
+wcdl_status wcdl_serve_begin(wcdl_engine* e);
+
+/* Queue facts (arity + 1 columns, instance id first) for the next step. */
+wcdl_status wcdl_serve_admit(wcdl_engine* e, uint32_t rel, const uint32_t* const* cols,
+                             uint64_t n_rows, int on_device);
+
+/* One round for every instance with work.  stats may be NULL. */
+wcdl_status wcdl_serve_step(wcdl_engine* e, wcdl_step_stats* stats);
+
+/* Instances that still have work (rows in some delta or admitted facts not yet
+ * stepped), ascending; writes min(count, cap) ids, *count receives the total.
+ * An admitted instance absent from this list has reached its fixpoint. */
+wcdl_status wcdl_serve_live(wcdl_engine* e, uint32_t* ids, uint64_t cap, uint64_t* count);
+
+/* Drop every row of the listed instances from every relation (frees their
+ * memory).  ids need not be sorted. */
+wcdl_status wcdl_serve_release(wcdl_engine* e, const uint32_t* ids, uint64_t n);
+
+/* Stop serving (relations keep their contents). */
+wcdl_status wcdl_serve_end(wcdl_engine* e);
+
 /* Sizes of a relation's per-round deltas in its (recursive) stratum during
  * the last run: |delta_0|, |delta_1|, ..., ending with the empty one.
  * Writes min(count, cap) entries; *count receives the total. */

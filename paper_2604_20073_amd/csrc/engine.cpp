@@ -232,6 +232,10 @@ struct wcdl_engine {
   // Rows produced per work unit by each rule version (rule, delta atom) the
   // last time it ran; sizes the count-pass staging arena.
   std::map<std::pair<uint32_t, int>, double> rows_per_unit;
+  // Serving state: one version per rule and body atom; admitted facts.
+  bool serving = false;
+  std::vector<wcdl::Version> serve_versions;
+  std::map<uint32_t, wcdl::Cols> pending;
 };
 
 namespace wcdl {
@@ -2089,6 +2093,177 @@ wcdl_status wcdl_autotune(wcdl_engine* e, const uint32_t* wg_per_cu, uint32_t n,
     e->cfg.wg_per_cu = best;
     if (chosen) *chosen = best;
     if (best_ms) *best_ms = bt;
+  });
+}
+
+wcdl_status wcdl_serve_begin(wcdl_engine* e) {
+  return guarded(e, [&] {
+    if (!batched(e)) throw Error(WCDL_E_STATE, "serving needs a batched engine");
+    for (auto& R : e->rels) {
+      R.full = copy_cols(e, R.base);
+      R.full_ord.clear();
+      R.delta_ord.clear();
+      R.delta_ord.emplace(canonical(R.arity), empty_cols(R.arity, canonical(R.arity)));
+      R.delta_sizes.clear();
+    }
+    e->serve_versions.clear();
+    for (u32 ri = 0; ri < e->rules.size(); ++ri)
+      for (u32 j = 0; j < e->rules[ri].body.size(); ++j) {
+        e->serve_versions.push_back(plan_version(e, ri, (int)j, e->cfg.flags));
+        e->serve_versions.back().sorted_output = false;
+      }
+    e->pending.clear();
+    e->serving = true;
+    sync_all(e);
+  });
+}
+
+wcdl_status wcdl_serve_admit(wcdl_engine* e, uint32_t rel, const uint32_t* const* cols,
+                             uint64_t n_rows, int on_device) {
+  return guarded(e, [&] {
+    if (!e->serving) throw Error(WCDL_E_STATE, "not serving");
+    if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
+    if (n_rows == 0) return;
+    if (!cols) throw Error(WCDL_E_INVALID, "null columns");
+    const u32 k = e->rels[rel].arity;
+    std::vector<DBuf<u32>> tmp;
+    std::vector<const u32*> dp;
+    for (u32 j = 0; j < k; ++j) {
+      if (!cols[j]) throw Error(WCDL_E_INVALID, "null column pointer");
+      tmp.emplace_back(e->mem.get(), n_rows);
+      WCDL_HIP(hipMemcpyAsync(tmp.back().get(), cols[j], n_rows * sizeof(u32),
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              e->streams[0]));
+      dp.push_back(tmp.back().get());
+    }
+    Cols srt = sort_rows(e, 0, canonical(k), dp, n_rows, true);
+    auto it = e->pending.find(rel);
+    if (it == e->pending.end()) {
+      e->pending.emplace(rel, std::move(srt));
+    } else {
+      Cols d = difference(e, 0, srt, it->second);
+      if (d.n) it->second = merged(e, 0, it->second, d);
+    }
+    sync_all(e);
+  });
+}
+
+wcdl_status wcdl_serve_step(wcdl_engine* e, wcdl_step_stats* out) {
+  return guarded(e, [&] {
+    if (!e->serving) throw Error(WCDL_E_STATE, "not serving");
+    auto t0 = Clock::now();
+    Stats st;
+    // Admitted facts not yet known join this round's deltas.
+    for (auto& kv : e->pending) {
+      Relation& R = e->rels[kv.first];
+      Cols d = difference(e, 0, kv.second, R.full);
+      const std::vector<u32> canon = canonical(R.arity);
+      Cols cur = empty_cols(R.arity, canon);
+      auto it = R.delta_ord.find(canon);
+      if (it != R.delta_ord.end()) cur = std::move(it->second);
+      commit_delta(e, kv.first, d, st);
+      Cols next = cur.n == 0 ? std::move(d) : (d.n ? merged(e, 0, cur, d) : std::move(cur));
+      R.delta_ord.clear();
+      R.delta_ord.emplace(canon, std::move(next));
+    }
+    e->pending.clear();
+    sync_all(e);
+    bool any = false;
+    for (auto& R : e->rels) {
+      auto it = R.delta_ord.find(canonical(R.arity));
+      if (it != R.delta_ord.end() && it->second.n) any = true;
+    }
+    wcdl_step_stats s{};
+    if (any) {
+      auto fresh = new_rows(e, e->serve_versions, st);
+      for (u32 rel = 0; rel < e->rels.size(); ++rel) {
+        Relation& R = e->rels[rel];
+        auto it = fresh.find(rel);
+        Cols d = it != fresh.end() ? std::move(it->second) : empty_cols(R.arity, canonical(R.arity));
+        commit_delta(e, rel, d, st);
+        s.new_rows += d.n;
+        R.delta_ord.clear();
+        R.delta_ord.emplace(canonical(R.arity), std::move(d));
+      }
+      sync_all(e);
+    }
+    for (auto& R : e->rels) s.resident_rows += R.full.n;
+    s.candidate_rows = st.candidates;
+    s.wall_ms = ms_since(t0);
+    if (out) *out = s;
+  });
+}
+
+wcdl_status wcdl_serve_live(wcdl_engine* e, uint32_t* ids, uint64_t cap, uint64_t* count) {
+  return guarded(e, [&] {
+    if (!e->serving) throw Error(WCDL_E_STATE, "not serving");
+    std::set<u32> live;
+    auto collect = [&](const Cols& c) {
+      if (c.n == 0) return;
+      const u32 pos0 = (u32)(std::find(c.order.begin(), c.order.end(), 0u) - c.order.begin());
+      DBuf<u32> out(e->mem.get(), c.n);
+      const u32* in = c.col[pos0].get();
+      u32* op = out.get();
+      // Distinct instance ids of a copy sorted with the instance column first.
+      u64 nd = unique_rows(ctx(e), 1, &in, c.n, &op);
+      std::vector<u32> h(nd);
+      WCDL_HIP(hipMemcpy(h.data(), out.get(), nd * sizeof(u32), hipMemcpyDeviceToHost));
+      live.insert(h.begin(), h.end());
+    };
+    for (auto& R : e->rels)
+      for (auto& kv : R.delta_ord)
+        if (!kv.first.empty() && kv.first[0] == 0) { collect(kv.second); break; }
+    for (auto& kv : e->pending) collect(kv.second);
+    u64 i = 0;
+    for (u32 v : live) {
+      if (ids && i < cap) ids[i] = v;
+      ++i;
+    }
+    if (count) *count = live.size();
+  });
+}
+
+wcdl_status wcdl_serve_release(wcdl_engine* e, const uint32_t* ids, uint64_t n) {
+  return guarded(e, [&] {
+    if (!e->serving) throw Error(WCDL_E_STATE, "not serving");
+    if (n == 0) return;
+    if (!ids) throw Error(WCDL_E_INVALID, "null ids");
+    std::vector<u32> h(ids, ids + n);
+    std::sort(h.begin(), h.end());
+    h.erase(std::unique(h.begin(), h.end()), h.end());
+    DBuf<u32> d_ids(e->mem.get(), h.size());
+    WCDL_HIP(hipMemcpy(d_ids.get(), h.data(), h.size() * sizeof(u32), hipMemcpyHostToDevice));
+    auto drop = [&](Cols& c) {
+      if (c.n == 0) return;
+      const u32 k = c.arity();
+      const u32 pos0 = (u32)(std::find(c.order.begin(), c.order.end(), 0u) - c.order.begin());
+      Cols out;
+      out.order = c.order;
+      std::vector<u32*> op;
+      for (u32 j = 0; j < k; ++j) {
+        out.col.emplace_back(e->mem.get(), c.n);
+        op.push_back(out.col.back().get());
+      }
+      auto ip = c.ptrs();
+      out.n = drop_leading(ctx(e), k, ip.data(), c.n, pos0, d_ids.get(), h.size(), op.data());
+      c = std::move(out);
+    };
+    for (auto& R : e->rels) {
+      drop(R.full);
+      drop(R.base);
+      for (auto& kv : R.full_ord) drop(kv.second);
+      for (auto& kv : R.delta_ord) drop(kv.second);
+    }
+    for (auto& kv : e->pending) drop(kv.second);
+    sync_all(e);
+  });
+}
+
+wcdl_status wcdl_serve_end(wcdl_engine* e) {
+  return guarded(e, [&] {
+    e->serving = false;
+    e->serve_versions.clear();
+    e->pending.clear();
   });
 }
 

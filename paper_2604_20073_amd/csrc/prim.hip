@@ -390,6 +390,19 @@ __global__ __launch_bounds__(WG) void k_merge_place(ColsIn a, ColsIn b, ColsOut 
   }
 }
 
+__global__ __launch_bounds__(WG) void k_keep_flags(const u32* lead, u64 n, const u32* ids,
+                                                   u64 nids, u32* flags) {
+  const u64 i = (u64)blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  const u32 v = lead[i];
+  u64 lo = 0, hi = nids;
+  while (lo < hi) {
+    u64 mid = lo + ((hi - lo) >> 1);
+    if (ids[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  flags[i] = (lo < nids && ids[lo] == v) ? 0u : 1u;
+}
+
 __global__ void k_lead_range(const u32* col, u64 n, u32 v, u64* out) {
   u64 lo = 0, hi = n;
   while (lo < hi) {
@@ -409,6 +422,23 @@ __global__ void k_lead_range(const u32* col, u64 n, u32 v, u64* out) {
 
 // ---------------------------------------------------------------------------
 // Launchers
+
+u64 drop_leading(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32 lead_col, const u32* ids,
+                 u64 nids, u32* const* out_cols) {
+  if (n == 0) return 0;
+  DBuf<u32> flags(c.mem, n);
+  DBuf<u64> pos(c.mem, n), total(c.mem, 1);
+  k_keep_flags<<<grid_for(n, WG), WG, 0, c.s>>>(in_cols[lead_col], n, ids, nids, flags.get());
+  WCDL_HIP(hipGetLastError());
+  scan_u32_excl(c, flags.get(), pos.get(), n, total.get());
+  k_compact<<<grid_for(n, WG), WG, 0, c.s>>>(cols_in(k, in_cols), cols_out(k, out_cols), k, n,
+                                              flags.get(), pos.get());
+  WCDL_HIP(hipGetLastError());
+  u64 h = 0;
+  WCDL_HIP(hipMemcpyAsync(&h, total.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
+  WCDL_HIP(hipStreamSynchronize(c.s));
+  return h;
+}
 
 void lead_range(Ctx c, const u32* col, u64 n, u32 v, u64* d_out) {
   k_lead_range<<<1, 1, 0, c.s>>>(col, n, v, d_out);

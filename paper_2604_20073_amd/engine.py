@@ -59,6 +59,11 @@ class _Stats(ctypes.Structure):
                 ("candidates_per_level", ctypes.c_uint64 * 8)]
 
 
+class _StepStats(ctypes.Structure):
+    _fields_ = [("candidate_rows", ctypes.c_uint64), ("new_rows", ctypes.c_uint64),
+                ("resident_rows", ctypes.c_uint64), ("wall_ms", ctypes.c_double)]
+
+
 class WcdlError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
@@ -73,7 +78,8 @@ EXPORTS = [
     "wcdl_add_rule", "wcdl_add_rules_text", "wcdl_rule_count", "wcdl_split_rule", "wcdl_run",
     "wcdl_relation_size", "wcdl_read_columns", "wcdl_delta_sizes", "wcdl_work_slice",
     "wcdl_owner_key", "wcdl_decode_unit", "wcdl_relation_range", "wcdl_read_rows",
-    "wcdl_autotune",
+    "wcdl_autotune", "wcdl_serve_begin", "wcdl_serve_admit", "wcdl_serve_step",
+    "wcdl_serve_live", "wcdl_serve_release", "wcdl_serve_end",
 ]
 
 
@@ -106,6 +112,12 @@ def lib():
     L.wcdl_relation_range.argtypes = [P, u32, u32, pu64, pu64]
     L.wcdl_read_rows.argtypes = [P, u32, u64, u64, ctypes.POINTER(P), ctypes.c_int]
     L.wcdl_autotune.argtypes = [P, pu32, u32, pu32, ctypes.POINTER(ctypes.c_double)]
+    L.wcdl_serve_begin.argtypes = [P]
+    L.wcdl_serve_admit.argtypes = [P, u32, ctypes.POINTER(P), u64, ctypes.c_int]
+    L.wcdl_serve_step.argtypes = [P, ctypes.POINTER(_StepStats)]
+    L.wcdl_serve_live.argtypes = [P, pu32, u64, pu64]
+    L.wcdl_serve_release.argtypes = [P, pu32, u64]
+    L.wcdl_serve_end.argtypes = [P]
     L.wcdl_work_slice.argtypes = [u64, u64, u64, pu64, pu64]
     L.wcdl_work_slice.restype = None
     L.wcdl_owner_key.argtypes = [pu64, u64, u64]
@@ -236,9 +248,7 @@ class Engine:
         return h.value
 
     # -- data --------------------------------------------------------------
-    def load(self, name: str, rows):
-        """Add facts: rows is an (n, arity) array of uint32 values (numpy,
-        or a torch tensor of 32-bit integers on the CPU or the GPU)."""
+    def _columns(self, name, rows):
         torch = self._torch
         k = self.arity[name]
         if isinstance(rows, torch.Tensor):
@@ -262,9 +272,45 @@ class Engine:
             n = a.shape[0]
             on_dev = 0
             keep = cols
-        arr = (ctypes.c_void_p * k)(*ptrs)
+        return (ctypes.c_void_p * k)(*ptrs), n, on_dev, keep
+
+    def load(self, name: str, rows):
+        """Add facts: rows is an (n, arity) array of uint32 values (numpy,
+        or a torch tensor of 32-bit integers on the CPU or the GPU); batched
+        engines take the instance id as an extra leading column."""
+        arr, n, on_dev, keep = self._columns(name, rows)
         self._check(self._lib.wcdl_load_columns(self._e, self.ids[name], arr, n, on_dev))
         del keep
+
+    # -- continuous evaluation (batched engines) ------------------------------
+    def serve_begin(self):
+        self._check(self._lib.wcdl_serve_begin(self._e))
+
+    def serve_admit(self, name: str, rows):
+        """Queue facts (instance id first) for the next step."""
+        arr, n, on_dev, keep = self._columns(name, rows)
+        self._check(self._lib.wcdl_serve_admit(self._e, self.ids[name], arr, n, on_dev))
+        del keep
+
+    def serve_step(self) -> dict:
+        s = _StepStats()
+        self._check(self._lib.wcdl_serve_step(self._e, ctypes.byref(s)))
+        return {"candidate_rows": s.candidate_rows, "new_rows": s.new_rows,
+                "resident_rows": s.resident_rows, "wall_ms": s.wall_ms}
+
+    def serve_live(self) -> list:
+        cnt = ctypes.c_uint64()
+        self._check(self._lib.wcdl_serve_live(self._e, None, 0, ctypes.byref(cnt)))
+        buf = (ctypes.c_uint32 * max(cnt.value, 1))()
+        self._check(self._lib.wcdl_serve_live(self._e, buf, cnt.value, ctypes.byref(cnt)))
+        return [int(buf[i]) for i in range(cnt.value)]
+
+    def serve_release(self, ids):
+        a = (ctypes.c_uint32 * max(len(ids), 1))(*ids)
+        self._check(self._lib.wcdl_serve_release(self._e, a, len(ids)))
+
+    def serve_end(self):
+        self._check(self._lib.wcdl_serve_end(self._e))
 
     def clear(self, name: str):
         self._check(self._lib.wcdl_clear_relation(self._e, self.ids[name]))

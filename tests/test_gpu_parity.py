@@ -370,3 +370,48 @@ def test_autotune_keeps_results():
     for n in ("tri", "q"):
         assert np.array_equal(e.read_numpy(n), expect[n])
     e.close()
+
+
+# --------------------------------------------------------------------------
+# Serving: requests join while others are in flight; each result equals the
+# request's least model alone.
+# --------------------------------------------------------------------------
+
+def test_served_results_equal_alone():
+    from paper_2604_20073_amd.serve import OUTPUTS, PROGRAMS, Server
+    trace = W.serving_trace(24, 400.0, 4242, m_lo=200, m_hi=3000)
+    facts = {r["id"]: W.serving_facts(r) for r in trace}
+    srv = Server(max_active=8)
+    res = srv.run(trace, facts, keep_results=True)
+    srv.close()
+    assert res["completed"] == len(trace)
+    for r in trace:
+        rels, rules = PROGRAMS[r["kind"]]
+        _, expect = oracle.evaluate(rels, rules, facts[r["id"]])
+        for o in OUTPUTS[r["kind"]]:
+            assert np.array_equal(res["rows"][r["id"]][o], expect[o]), (r["id"], r["kind"])
+    assert res["steps"] > 3
+
+
+def test_serve_release_and_live():
+    e = Engine(batched=True)
+    e.declare("edge", 2)
+    e.declare("path", 2)
+    e.add_rules(TC)
+    e.serve_begin()
+    g = W.path_graph(6)
+    e.serve_admit("edge", np.concatenate([np.full((5, 1), 7, np.uint32), g], axis=1))
+    steps = 0
+    while 7 in e.serve_live() or steps == 0:
+        e.serve_step()
+        steps += 1
+        if steps == 2:  # a second instance joins while the first is in flight
+            e.serve_admit("edge", np.concatenate([np.full((5, 1), 9, np.uint32), g], axis=1))
+    assert len(e.read_instance("path", 7)) == 15
+    while e.serve_live():
+        e.serve_step()
+    assert len(e.read_instance("path", 9)) == 15
+    e.serve_release([7])
+    assert e.range("path", 7)[1] == 0 and len(e.read_instance("path", 9)) == 15
+    e.serve_end()
+    e.close()
