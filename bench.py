@@ -116,6 +116,9 @@ def bench_andersen(args):
     for n in ("addressOf", "assign", "load", "store", "pt"):
         e.declare(n, 2)
     e.add_rules(ANDERSEN)
+    if args.split:
+        e.split_rule(2, [0, 1])  # helper(v,q) :- load(v,p), pt(p,q)
+        e.split_rule(3, [0, 1])  # helper(w,q) :- store(p,w), pt(p,q)
     for n, t in dev.items():
         e.load(n, t)
     for i in range(args.warmup):
@@ -136,7 +139,8 @@ def bench_andersen(args):
            "unit": "tuples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-           "config": {"workload": "andersen points-to: 1M vars, 200k heaps, 3.5M input tuples",
+           "config": {"workload": "andersen points-to: 1M vars, 200k heaps, 3.5M input tuples"
+                                  + (" (load/store rules split)" if args.split else ""),
                       "pt": n_pt, "rounds": stats[0]["rounds"],
                       "candidate_rows": stats[0]["candidate_rows"]},
            "phase_ms": phases,
@@ -309,6 +313,9 @@ def main():
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=256,
                     help="batch workload: instances timed one at a time on the plain engine")
+    ap.add_argument("--split", action="store_true",
+                    help="andersen: factor load(v,p), pt(p,q) and store(p,w), pt(p,q) into helper "
+                         "relations (the paper's helper-relation split); same pt")
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--m-max", type=float, default=1e5)

@@ -977,9 +977,9 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     ~Staging() { for (auto* p : v) (void)hipHostFree(p); }
   } guard{staging};
 
-  auto t_hist = Clock::now();
+  auto t_index = Clock::now();
   // ---- Inputs: every version's sorted copies.  Missing column orders are
-  // built on stream 0; fence it before any other stream reads them.
+  // built on stream 0 (Build Index); fence it before other streams read them.
   for (size_t i = 0; i < vs.size(); ++i) {
     VRun& R = runs[i];
     Version& v = vs[i];
@@ -1011,6 +1011,8 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
       }
   }
   WCDL_HIP(hipStreamSynchronize(e->streams[0]));
+  st.phase[WCDL_PH_INDEX] += ms_since(t_index);
+  auto t_hist = Clock::now();
   // ---- Phase A: plan upload, constant narrowing, root-key flags.
   for (size_t i = 0; i < vs.size(); ++i) {
     VRun& R = runs[i];

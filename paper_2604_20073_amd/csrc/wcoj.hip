@@ -724,16 +724,18 @@ __global__ __launch_bounds__(WG) void k_key_compact(const u32* col, const u32* f
 
 __global__ void k_key_end(const u32* rng0, u32 atom, u64 K, u32* S) { S[K] = rng0[2 * atom + 1]; }
 
-// dir[v] = first row with value >= v.  Row r writes the entries for the
-// values in (col[r-1], col[r]]; the last row also writes (col[n-1], vmax+1].
+// dir[v] = first row with value >= v, one thread per entry v in [0, vmax+1]
+// (a lower bound search; adjacent threads walk nearly the same path, so the
+// upper levels of the search stay in cache).
 __global__ __launch_bounds__(WG) void k_build_dir(const u32* col, u64 n, u32 vmax, u32* dir) {
-  const u64 r = (u64)blockIdx.x * WG + threadIdx.x;
-  if (r >= n) return;
-  const u32 v = col[r];
-  const u64 from = r ? (u64)col[r - 1] + 1 : 0;
-  for (u64 u = from; u <= v && u <= vmax; ++u) dir[u] = (u32)r;
-  if (r == n - 1)
-    for (u64 u = (u64)v + 1; u <= (u64)vmax + 1; ++u) dir[u] = (u32)n;
+  const u64 v = (u64)blockIdx.x * WG + threadIdx.x;
+  if (v > (u64)vmax + 1) return;
+  u64 lo = 0, hi = n;
+  while (lo < hi) {
+    const u64 mid = lo + ((hi - lo) >> 1);
+    if ((u64)col[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  dir[v] = (u32)lo;
 }
 
 u32 grid1(u64 n) {
@@ -773,7 +775,7 @@ void join_root_compact(Ctx c, const u32* col, const u32* d_rng0, u32 atom, u32 n
 
 void build_directory(Ctx c, const u32* col, u64 n, u32 vmax, u32* dir) {
   if (n == 0) return;
-  k_build_dir<<<grid1(n), WG, 0, c.s>>>(col, n, vmax, dir);
+  k_build_dir<<<grid1((u64)vmax + 2), WG, 0, c.s>>>(col, n, vmax, dir);
   WCDL_HIP(hipGetLastError());
 }
 

@@ -279,3 +279,20 @@ def test_rejects_unsafe_and_malformed_rules():
         o.add_rules("p(x) :- edge(x,y).")
     with pytest.raises(oracle.OracleError):
         o.add_rules("p(x,y) :- nosuch(x,y).")
+
+
+def test_helper_split_pointsto_same_model():
+    """The paper's helper-relation split (Sec. 5) of the load and store
+    rules leaves pt unchanged (checked on the oracle and the worklist solver)."""
+    from paper_2604_20073_amd.serve import PROGRAMS
+    rels, rules = PROGRAMS["pt"]
+    for seed in range(3):
+        rel = W.andersen(700 + seed, n_modules=3, vars_per_module=40, heaps_per_module=9,
+                         n_address_of=30, n_assign=90, n_load=30, n_store=30)
+        _, split = oracle.evaluate(rels, rules, rel)
+        _, plain = oracle.evaluate({"addressOf": 2, "assign": 2, "load": 2, "store": 2, "pt": 2},
+                                   ANDERSEN, rel)
+        assert np.array_equal(split["pt"], plain["pt"])
+        expect = as_sorted_array(points_to(rel["addressOf"], rel["assign"], rel["load"],
+                                           rel["store"]), 2)
+        assert np.array_equal(split["pt"], expect)
