@@ -314,8 +314,9 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=256,
                     help="batch workload: instances timed one at a time on the plain engine")
     ap.add_argument("--split", action="store_true",
-                    help="andersen: factor load(v,p), pt(p,q) and store(p,w), pt(p,q) into helper "
-                         "relations (the paper's helper-relation split); same pt")
+                    help="helper-relation split (same results): rmat: factor edge(w,x), edge(x,z), "
+                         "edge(w,z) of q into ascending triangles; andersen: factor load(v,p), "
+                         "pt(p,q) and store(p,w), pt(p,q)")
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--m-max", type=float, default=1e5)
@@ -369,6 +370,11 @@ def main():
     e.declare("tri", 3)
     e.declare("q", 4)
     e.add_rules(TRI + "\n" + Q4)
+    if args.split:
+        # Helper-relation split of q: H(w,x,z) :- edge(w,x), edge(x,z), edge(w,z)
+        # with the implied w < x < z pushed down (ascending triangles); the
+        # leaf then intersects H(w,x,.) with N(y).
+        e.split_rule(1, [0, 4, 5])
 
     def step():
         e.clear("edge")
@@ -435,7 +441,8 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": (f"rmat-{args.scale} {args.edges} edges: tri + 4-clique "
-                                "(non-recursive, skewed cyclic joins)"),
+                                "(non-recursive, skewed cyclic joins)"
+                                + ("; q split through ascending triangles" if args.split else "")),
                    "nodes": 1 << args.scale, "edges": int(len(edges)),
                    "tri": n_tri, "q": n_q, "derived": derived},
         "roofline": roofline,

@@ -1956,6 +1956,34 @@ wcdl_status wcdl_split_rule(wcdl_engine* e, uint32_t rule_id, const uint32_t* at
         if (c.b.var) outer.insert(c.b.v);
       }
     }
+    // Orders implied by the rule's comparisons (transitive closure over
+    // variable-variable < and <=) among the selected atoms' variables are
+    // copied into the helper: every binding the rule uses satisfies them, so
+    // the helper may drop rows that do not (the rule keeps its own copies).
+    {
+      const u32 nv = r.nvars;
+      std::vector<std::vector<int>> ord(nv, std::vector<int>(nv, -1));  // -1 none, 0 <=, 1 <
+      for (auto& c : r.cmps)
+        if (c.a.var && c.b.var && c.op != OP_NE && c.a.v != c.b.v)
+          ord[c.a.v][c.b.v] = std::max(ord[c.a.v][c.b.v], c.op == OP_LT ? 1 : 0);
+      for (u32 k = 0; k < nv; ++k)
+        for (u32 i = 0; i < nv; ++i)
+          for (u32 j = 0; j < nv; ++j)
+            if (ord[i][k] >= 0 && ord[k][j] >= 0 && i != j)
+              ord[i][j] = std::max(ord[i][j], std::max(ord[i][k], ord[k][j]));
+      for (u32 i : inner)
+        for (u32 j : inner) {
+          if (i == j || ord[i][j] < 0 || helper_cmps.size() >= (size_t)WCDL_MAX_CMPS) continue;
+          Cmp c;
+          c.op = ord[i][j] == 1 ? OP_LT : OP_LE;
+          c.a = Term{true, i};
+          c.b = Term{true, j};
+          bool dup = false;
+          for (auto& h : helper_cmps)
+            if (h.op == c.op && h.a.var && h.b.var && h.a.v == i && h.b.v == j) dup = true;
+          if (!dup) helper_cmps.push_back(c);
+        }
+    }
     std::vector<u32> shared;  // in order of first occurrence in the selected atoms
     for (u32 a : sel)
       for (auto& t : r.body[a].t)

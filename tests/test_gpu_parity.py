@@ -415,3 +415,25 @@ def test_serve_release_and_live():
     assert e.range("path", 7)[1] == 0 and len(e.read_instance("path", 9)) == 15
     e.serve_end()
     e.close()
+
+
+def test_split_q_through_ascending_triangles():
+    """q(w,x,y,z) split with the helper H(w,x,z) :- edge(w,x), edge(x,z),
+    edge(w,z): the implied w < x < z is pushed into the helper, q unchanged."""
+    edges = W.rmat_graph(12, 40000, 55)
+    rules = TRI + "\n" + Q4
+    _, expect = oracle.evaluate({"edge": 2, "tri": 3, "q": 4}, rules, {"edge": edges})
+    e = Engine()
+    for n, k in {"edge": 2, "tri": 3, "q": 4}.items():
+        e.declare(n, k)
+    e.add_rules(rules)
+    h = e.split_rule(1, [0, 4, 5])
+    e.load("edge", edges)
+    e.run()
+    assert np.array_equal(e.read_numpy("q"), expect["q"])
+    assert np.array_equal(e.read_numpy("tri"), expect["tri"])
+    e.arity["H"] = 3
+    e.ids["H"] = h
+    H = e.read_numpy("H")
+    assert np.all(H[:, 0] < H[:, 1]) and np.all(H[:, 1] < H[:, 2])  # ascending triangles only
+    e.close()
