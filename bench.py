@@ -313,10 +313,11 @@ def main():
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=256,
                     help="batch workload: instances timed one at a time on the plain engine")
-    ap.add_argument("--split", action="store_true",
-                    help="helper-relation split (same results): rmat: factor edge(w,x), edge(x,z), "
-                         "edge(w,z) of q into ascending triangles; andersen: factor load(v,p), "
-                         "pt(p,q) and store(p,w), pt(p,q)")
+    ap.add_argument("--no-split", dest="split", action="store_false",
+                    help="evaluate the rules as written, without the helper-relation split "
+                         "(Sec. 5) that the runs use by default (same results): rmat: factor "
+                         "edge(w,x), edge(x,z), edge(w,z) of q into ascending triangles; "
+                         "andersen: factor load(v,p), pt(p,q) and store(p,w), pt(p,q)")
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--m-max", type=float, default=1e5)

@@ -955,7 +955,8 @@ void repartition(Engine* e, VRun& R, u64 max_rows, Stats& st) {
 }
 
 // Raw head rows of one chunk (canonical column order, unsorted unless
-// `presorted`: sorted, unique, and the head's entire output).
+// `presorted`: sorted, unique, above every row of the head's earlier chunks,
+// and from the head's only version).
 using Sink = std::function<void(u32 rel, Cols&& rows, bool presorted)>;
 
 // Evaluate a set of rule versions over the current relations and hand every
@@ -1194,9 +1195,24 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
   WCDL_HIP(hipMemGetInfo(&free_b, &total_b));
   const u64 chunk_bytes = e->cfg.mem_budget_bytes ? e->cfg.mem_budget_bytes / 4
                                                   : (u64)(total_b * 0.06);
+  // A head written by one version whose rows come out sorted and unique,
+  // into an empty relation, needs no scratch beyond its final size: it is
+  // written whole unless that size itself is large against the memory.
+  std::map<u32, bool> in_order;
+  for (auto& R : runs)
+    if (!R.skip) {
+      auto it = in_order.find(R.v->head_rel);
+      bool ok = nver[R.v->head_rel] == 1 && R.v->sorted_output &&
+                e->rels[R.v->head_rel].full.n == 0;
+      in_order[R.v->head_rel] = it == in_order.end() ? ok : it->second && ok;
+    }
+  const u64 direct_bytes = e->cfg.mem_budget_bytes ? e->cfg.mem_budget_bytes / 2 : (u64)(free_b / 2);
   std::set<u32> chunked;
-  for (auto& kv : rows)
-    if (kv.second * e->rels[kv.first].arity * 4ull > chunk_bytes) chunked.insert(kv.first);
+  for (auto& kv : rows) {
+    const u64 bytes = kv.second * e->rels[kv.first].arity * 4ull;
+    if (bytes > chunk_bytes && !(in_order[kv.first] && bytes <= direct_bytes))
+      chunked.insert(kv.first);
+  }
   std::map<u32, Cols> whole;
   for (auto& kv : rows) {
     if (chunked.count(kv.first)) continue;
@@ -1332,7 +1348,8 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
       t.collect(st);
       st.candidates += chunk.n;
       st.phase[WCDL_PH_MATERIALIZE] += ms_since(t_chunk);
-      sink(R.v->head_rel, std::move(chunk), false);
+      // Ranges go in workgroup order, so a sorted head's chunks ascend.
+      sink(R.v->head_rel, std::move(chunk), in_order[R.v->head_rel]);
       recycle(e);
     }
     // The staging arena of this version is no longer needed.
@@ -1366,8 +1383,10 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
 void absorb_chunk(Engine* e, u32 rel, Cols&& rows, bool presorted, Cols& acc, Stats& st) {
   Relation& R = e->rels[rel];
   auto t = Clock::now();
-  if (presorted && R.full.n == 0 && acc.n == 0) {
-    acc = std::move(rows);
+  if (presorted && R.full.n == 0) {
+    // Ascending disjoint chunks: nothing to sort or subtract.
+    if (acc.n == 0) acc = std::move(rows);
+    else if (rows.n) acc = merged(e, 0, acc, rows);
   } else {
     Cols srt = sort_rows(e, 0, rows.order, std::vector<const u32*>(rows.ptrs()), rows.n, true);
     rows = Cols();

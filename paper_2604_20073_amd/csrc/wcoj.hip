@@ -31,12 +31,28 @@ namespace wcdl {
 namespace {
 
 constexpr int WG = 256;
+constexpr int LEAF_K = 4;  // leaf candidates per lane and step
 constexpr u32 UMAX = 0xffffffffu;
+
+// Reads of device columns through the global address space.  The column
+// pointers come out of the plan structure, so the compiler would otherwise
+// emit flat loads, which share the LDS wait counter: every LDS read would
+// then also wait for all outstanding column reads.
+typedef const u32 __attribute__((address_space(1))) gu32;
+typedef const u64 __attribute__((address_space(1))) gu64;
+__device__ inline u32 ldg(const u32* p) { return *(gu32*)p; }
+__device__ inline u64 ldg(const u64* p) { return *(gu64*)p; }
+
+// Wave-uniform copies of values the compiler cannot prove uniform (they come
+// from LDS), so that plan fields indexed by them are read with scalar loads.
+__device__ inline u32 uni(u32 x) { return (u32)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ inline int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline u64 uni(u64 x) { return ((u64)uni((u32)(x >> 32)) << 32) | uni((u32)x); }
 
 __device__ inline u32 lower_bound_u32(const u32* col, u32 lo, u32 hi, u32 v) {
   while (lo < hi) {
     u32 mid = lo + ((hi - lo) >> 1);
-    if (col[mid] < v) lo = mid + 1; else hi = mid;
+    if (ldg(col + mid) < v) lo = mid + 1; else hi = mid;
   }
   return lo;
 }
@@ -44,7 +60,7 @@ __device__ inline u32 lower_bound_u32(const u32* col, u32 lo, u32 hi, u32 v) {
 __device__ inline u32 upper_bound_u32(const u32* col, u32 lo, u32 hi, u32 v) {
   while (lo < hi) {
     u32 mid = lo + ((hi - lo) >> 1);
-    if (col[mid] <= v) lo = mid + 1; else hi = mid;
+    if (ldg(col + mid) <= v) lo = mid + 1; else hi = mid;
   }
   return lo;
 }
@@ -54,7 +70,7 @@ __device__ inline u32 upper_bound_u32(const u32* col, u32 lo, u32 hi, u32 v) {
 __device__ inline u32 gallop_past(const u32* col, u32 lo, u32 hi, u32 v) {
   u32 a = lo;
   u64 b = lo, step = 1;
-  while (b < hi && col[b] <= v) {
+  while (b < hi && ldg(col + b) <= v) {
     a = (u32)b + 1;
     b = (u64)a + step;
     step <<= 1;
@@ -146,6 +162,32 @@ __device__ inline u32 operand(const Bufs& B, const DOperand& o, int L, u32 i, u3
   return B.val(L - 1, o.v, i);
 }
 
+// Column of source s of a level (s varies per lane; the level does not).
+// The pointers are read as wave-uniform values and selected in registers; a
+// per-lane indexed read of the plan would put a dependent memory access in
+// front of every column read.
+__device__ inline const u32* source_col(const DLevel& lv, u32 s) {
+  const u32* col = (const u32*)uni((u64)lv.src[0].col);
+  for (u32 t = 1; t < lv.nsrc; ++t) {
+    const u32* c = (const u32*)uni((u64)lv.src[t].col);
+    if (s == t) col = c;
+  }
+  return col;
+}
+
+// Item of a level buffer owning candidate g: the first i with pre[i] > g,
+// pre being the inclusive prefix of the items' candidate counts (g < pre[n-1]).
+// The number of steps depends on n only.
+__device__ inline u32 owner_item(const u64* pre, u32 n, u64 g) {
+  u32 base = 0;
+  while (n > 1) {
+    const u32 half = n >> 1;
+    base = pre[base + half] <= g ? base + half : base;
+    n -= half;
+  }
+  return base + (pre[base] <= g ? 1u : 0u);
+}
+
 // Candidate v for level L (from parent item i, or the root when L == 0):
 // the driver source `drv` supplies it at row r (its run of equal values ends
 // at dhi if known, else NONE); every other source of the level must contain
@@ -183,12 +225,12 @@ __device__ inline bool try_candidate(const DPlan* P, const Bufs& B, int L, u32 i
       if ((u32)s == drv) {
         lo = B.lo(L - 1, a, i);
         // Only the first row of a run of equal values yields the candidate.
-        if (!last && r > lo && col[r - 1] == v) return false;
+        if (!last && r > lo && ldg(col + r - 1) == v) return false;
         hi = B.hi(L - 1, a, i);
         lo = r;
         if (last) hi = r + 1;
         else if (dhi != NONE) hi = dhi;
-        else if (src.dir) hi = src.dir[v + 1];
+        else if (src.dir) hi = ldg(src.dir + v + 1);
         else hi = gallop_past(col, r + 1, hi, v);
       } else if (src.alias != NONE) {
         // Same column and same range as an earlier source: same result.
@@ -197,14 +239,14 @@ __device__ inline bool try_candidate(const DPlan* P, const Bufs& B, int L, u32 i
       } else if (src.dir) {
         // Unnarrowed first column: the directory gives the run directly.
         if (v > src.dmax) return false;
-        lo = src.dir[v];
-        hi = src.dir[v + 1];
+        lo = ldg(src.dir + v);
+        hi = ldg(src.dir + v + 1);
         if (lo >= hi) return false;
       } else {
         lo = B.lo(L - 1, a, i);
         hi = B.hi(L - 1, a, i);
         u32 p = lower_bound_u32(col, lo, hi, v);
-        if (p >= hi || col[p] != v) return false;
+        if (p >= hi || ldg(col + p) != v) return false;
         lo = p;
         hi = last ? p + 1 : gallop_past(col, p + 1, hi, v);
       }
@@ -257,8 +299,8 @@ __device__ inline bool prepare_item(const DPlan* P, const Bufs& B, int L, u32 i,
       const DSource& src = nx.src[s];
       if (src.dir) {
         // Unnarrowed first column: clip through the directory.
-        if (lov) lo = lov <= src.dmax ? src.dir[lov] : hi;
-        if (hiv < src.dmax) hi = src.dir[hiv + 1];
+        if (lov) lo = lov <= src.dmax ? ldg(src.dir + lov) : hi;
+        if (hiv < src.dmax) hi = ldg(src.dir + hiv + 1);
       } else {
         if (lov) lo = lower_bound_u32(src.col, lo, hi, lov);
         if (hiv != UMAX) hi = upper_bound_u32(src.col, lo, hi, hiv);
@@ -356,21 +398,37 @@ __device__ inline u64 rank_alive(bool alive, WgState& st, u64* tot) {
 
 // One chunk of output candidates, called by every thread: count them
 // (mode 0), write them at their final offsets (mode 1), or count them and
-// stage them in arena chunks (mode 2).  Rows keep traversal order.
-template <int MODE>
-__device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, int L, u32 i,
-                                  u32 v, bool alive, u64 obase, u64 b, u64& my_count) {
+// stage them in arena chunks (mode 2).  Lane t holds candidates t + k*WG of
+// the chunk (k < K); rows keep that order, which is traversal order.
+template <int MODE, int K>
+__device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, int L,
+                                  const u32 (&i)[K], const u32 (&v)[K], const bool (&alive)[K],
+                                  u64 obase, u64 b, u64& my_count) {
+  static_assert(K * WG <= STAGE_CHUNK && WG < 65536 && K <= 4, "ranks are packed in 16 bits");
   if (MODE == 0) {
-    my_count += alive ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) my_count += alive[k] ? 1 : 0;
     return;
   }
-  u64 tot;
-  const u64 rk = rank_alive(alive, st, &tot);
+  // One scan ranks all K sub-chunks: field k (16 bits) counts sub-chunk k.
+  u64 x = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) x |= (u64)(alive[k] ? 1 : 0) << (16 * k);
+  u64 tots;
+  const u64 rks = block_excl_scan(x, st.sh, &tots);
+  u64 rk[K], tot = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    rk[k] = tot + ((rks >> (16 * k)) & 0xffffu);
+    tot += (tots >> (16 * k)) & 0xffffu;
+  }
   if (MODE == 1) {
-    if (alive) emit_row(P, B, L, i, v, obase + st.out + rk);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (alive[k]) emit_row(P, B, L, i[k], v[k], obase + st.out + rk[k]);
   } else {
     if (threadIdx.x == 0 && !st.ovf && st.out + tot > st.covered) {
-      // tot <= WG <= STAGE_CHUNK: at most one new chunk per call.
+      // tot <= K*WG <= STAGE_CHUNK: at most one new chunk per call.
       const u64 c = atomicAdd(reinterpret_cast<unsigned long long*>(P->stage_next), 1ull);
       if (c >= P->stage_chunks) {
         st.ovf = 1;
@@ -382,15 +440,115 @@ __device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, in
       }
     }
     __syncthreads();
-    if (alive && !st.ovf) {
-      const u64 r = st.out + rk;
-      const u64 c = st.chunk[(r / STAGE_CHUNK) & 1];
-      stage_row(P, B, L, i, v, c * STAGE_CHUNK + (r % STAGE_CHUNK));
+    if (!st.ovf) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (alive[k]) {
+          const u64 r = st.out + rk[k];
+          const u64 c = st.chunk[(r / STAGE_CHUNK) & 1];
+          stage_row(P, B, L, i[k], v[k], c * STAGE_CHUNK + (r % STAGE_CHUNK));
+        }
+      }
     }
   }
   __syncthreads();
   if (threadIdx.x == 0) st.out += tot;
   __syncthreads();
+}
+
+// Leaf candidates g0 + t + k*WG (lane t, k < K) of buffer bl: the parent
+// item, the value, and whether every source of the leaf level holds it.  The
+// K lookups of a lane proceed in lockstep, so each step has K independent
+// memory reads in flight instead of one.  At the leaf every source's column
+// is its last, so only membership matters: no ranges are narrowed.
+template <int K>
+__device__ inline void leaf_probe(const DPlan* P, const Bufs& B, int L, int bl, u32 nb, u64 g0,
+                                  u64 total, u32 (&it)[K], u32 (&v)[K], bool (&alive)[K]) {
+  const DLevel& lv = P->lvl[L];
+  const u64* pre = reinterpret_cast<const u64*>(B.sm + P->off_pre[bl]);
+  u64 g[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    g[k] = g0 + (u64)k * WG + threadIdx.x;
+    alive[k] = g[k] < total;
+    if (!alive[k]) g[k] = total - 1;  // searched like the rest, then dropped
+  }
+  // Owning item: first i with pre[i] > g (the step count depends on nb only,
+  // so the K searches advance together).
+  u32 base[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) base[k] = 0;
+  for (u32 n = nb; n > 1;) {
+    const u32 half = n >> 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) base[k] = pre[base[k] + half] <= g[k] ? base[k] + half : base[k];
+    n -= half;
+  }
+  u32 drv[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const u32 i = base[k] + (pre[base[k]] <= g[k] ? 1u : 0u);
+    it[k] = i;
+    const u64 gb = i ? pre[i - 1] : 0;
+    const u32 r = B.sm[P->off_clo[bl] + i] + (u32)(g[k] - gb);
+    drv[k] = B.sm[P->off_drv[bl] + i];
+    v[k] = alive[k] ? ldg(source_col(lv, drv[k]) + r) : 0;
+  }
+  for (u32 f = 0; f < lv.nne; ++f) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (v[k] == operand(B, lv.ne[f], L, it[k], v[k])) alive[k] = false;
+  }
+  for (u32 s = 0; s < lv.nsrc; ++s) {
+    const DSource& src = lv.src[s];
+    if (src.alias != NONE) continue;  // same column and range as an earlier source
+    const u32* col = src.col;
+    if (src.dir) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (alive[k] && drv[k] != s) {
+          if (v[k] > src.dmax || ldg(src.dir + v[k]) >= ldg(src.dir + v[k] + 1)) alive[k] = false;
+        }
+      }
+      continue;
+    }
+    u32 lo[K], hi[K];
+    bool run[K], found[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const bool act = alive[k] && drv[k] != s;
+      lo[k] = act ? B.lo(L - 1, src.atom, it[k]) : 0;
+      hi[k] = act ? B.hi(L - 1, src.atom, it[k]) : 0;
+      run[k] = lo[k] < hi[k];
+      found[k] = !act;
+    }
+    for (;;) {
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < K; ++k) any = any || run[k];
+      if (!any) break;
+      u32 mid[K], x[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        mid[k] = lo[k] + ((hi[k] - lo[k]) >> 1);
+        x[k] = run[k] ? ldg(col + mid[k]) : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (run[k]) {
+          if (x[k] == v[k]) {
+            found[k] = true;
+            run[k] = false;
+          } else {
+            if (x[k] < v[k]) lo[k] = mid[k] + 1; else hi[k] = mid[k];
+            run[k] = lo[k] < hi[k];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) alive[k] = alive[k] && found[k];
+  }
 }
 
 template <int MODE>
@@ -403,8 +561,8 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
   const int m = (int)P->m;
   u64 us, ue;
   if (part.balance_off) {
-    us = b ? rs.C[b - 1] : 0;
-    ue = rs.C[b];
+    us = b ? ldg(rs.C + b - 1) : 0;
+    ue = ldg(rs.C + b);
   } else {
     us = b * part.slice;
     ue = us + part.slice < rs.T ? us + part.slice : rs.T;
@@ -433,27 +591,29 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
   int bl = -1;       // buffer being drained; -1 = root keys
 
   for (;;) {
+    bl = uni(bl);
     if (bl < 0) {
-      if (st.key_next > klast) break;
+      if (uni(st.key_next) > klast) break;
       if (threadIdx.x == 0) st.n[0] = 0;
       __syncthreads();
       // Root keys -> level-0 items (or output rows when m == 1).
-      while (st.key_next <= klast && (m == 1 || st.n[0] + WG <= P->cap)) {
-        const u64 kk = st.key_next + threadIdx.x;
+      while (uni(st.key_next) <= klast && (m == 1 || uni(st.n[0]) + WG <= P->cap)) {
+        const u64 kk = uni(st.key_next) + threadIdx.x;
         bool alive = kk <= klast;
         u32 v = 0, drv = 0, clo = 0, chi = 0;
         R8 slo{}, shi{};
         if (alive) {
-          v = rs.U[kk];
-          alive = try_candidate(P, B, 0, 0, v, P->root_src, rs.S[kk], rs.S[kk + 1], slo, shi);
+          v = ldg(rs.U + kk);
+          alive = try_candidate(P, B, 0, 0, v, P->root_src, ldg(rs.S + kk), ldg(rs.S + kk + 1),
+                                slo, shi);
         }
-        const u64 cs = (alive && kk) ? rs.C[kk - 1] : 0;
+        const u64 cs = (alive && kk) ? ldg(rs.C + kk - 1) : 0;
         if (alive && m == 1) {
           alive = cs >= us && cs < ue;  // its single unit lies in this slice
         } else if (alive) {
           alive = prepare_item(P, B, 0, 0, v, slo, shi, &drv, &clo, &chi);
           if (alive) {
-            const u64 ce = rs.C[kk];
+            const u64 ce = ldg(rs.C + kk);
             const u64 lo = cs > us ? cs : us, hi = ce < ue ? ce : ue;
             alive = lo < hi;
             const u32 c0 = clo;
@@ -462,7 +622,9 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
           }
         }
         if (m == 1) {
-          emit_chunk<MODE>(P, B, st, 0, 0, v, alive, obase, b, my_count);
+          const u32 ia[1] = {0}, va[1] = {v};
+          const bool aa[1] = {alive};
+          emit_chunk<MODE, 1>(P, B, st, 0, ia, va, aa, obase, b, my_count);
         } else {
           u64 tot;
           u64 rk = rank_alive(alive, st, &tot);
@@ -480,13 +642,13 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
       continue;
     }
 
-    if (st.cur[bl] >= st.total[bl]) {  // buffer drained: go up
+    if (uni(st.cur[bl]) >= uni(st.total[bl])) {  // buffer drained: go up
       bl -= 1;
       continue;
     }
     const int L = bl + 1;  // level whose variable the candidates bind
     const u64* pre = reinterpret_cast<const u64*>(sm + P->off_pre[bl]);
-    const u32 nb = st.n[bl];
+    const u32 nb = uni(st.n[bl]);
 
     if (L == m - 1) {
       // Leaf level: every surviving candidate is an output row.
@@ -497,27 +659,12 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
         __syncthreads();
         continue;
       }
-      const u64 total = st.total[bl];
-      for (u64 g0 = st.cur[bl]; g0 < total; g0 += WG) {
-        const u64 g = g0 + threadIdx.x;
-        bool alive = g < total;
-        u32 i = 0, v = 0;
-        R8 slo{}, shi{};
-        if (alive) {
-          // Item owning candidate g: first i with pre[i] > g.
-          u32 lo = 0, hi = nb;
-          while (lo < hi) {
-            u32 mid = (lo + hi) >> 1;
-            if (pre[mid] <= g) lo = mid + 1; else hi = mid;
-          }
-          i = lo;
-          const u64 gb = i ? pre[i - 1] : 0;
-          const u32 r = sm[P->off_clo[bl] + i] + (u32)(g - gb);
-          const u32 drv = sm[P->off_drv[bl] + i];
-          v = P->lvl[L].src[drv].col[r];
-          alive = try_candidate(P, B, L, i, v, drv, r, NONE, slo, shi);
-        }
-        emit_chunk<MODE>(P, B, st, L, i, v, alive, obase, b, my_count);
+      const u64 total = uni(st.total[bl]);
+      for (u64 g0 = uni(st.cur[bl]); g0 < total; g0 += LEAF_K * WG) {
+        u32 i[LEAF_K], v[LEAF_K];
+        bool alive[LEAF_K];
+        leaf_probe<LEAF_K>(P, B, L, bl, nb, g0, total, i, v, alive);
+        emit_chunk<MODE, LEAF_K>(P, B, st, L, i, v, alive, obase, b, my_count);
       }
       if (threadIdx.x == 0) st.cur[bl] = total;
       __syncthreads();
@@ -527,23 +674,18 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
     // Inner level: expand candidates of buffer bl into buffer bl+1.
     if (threadIdx.x == 0) st.n[L] = 0;
     __syncthreads();
-    while (st.cur[bl] < st.total[bl] && st.n[L] + WG <= P->cap) {
-      const u64 total = st.total[bl];
-      const u64 g = st.cur[bl] + threadIdx.x;
+    while (uni(st.cur[bl]) < uni(st.total[bl]) && uni(st.n[L]) + WG <= P->cap) {
+      const u64 total = uni(st.total[bl]);
+      const u64 g = uni(st.cur[bl]) + threadIdx.x;
       bool alive = g < total;
       u32 i = 0, v = 0, drv2 = 0, clo = 0, chi = 0;
       R8 slo{}, shi{};
       if (alive) {
-        u32 lo = 0, hi = nb;
-        while (lo < hi) {
-          u32 mid = (lo + hi) >> 1;
-          if (pre[mid] <= g) lo = mid + 1; else hi = mid;
-        }
-        i = lo;
+        i = owner_item(pre, nb, g);
         const u64 gb = i ? pre[i - 1] : 0;
         const u32 r = sm[P->off_clo[bl] + i] + (u32)(g - gb);
         const u32 drv = sm[P->off_drv[bl] + i];
-        v = P->lvl[L].src[drv].col[r];
+        v = ldg(source_col(P->lvl[L], drv) + r);
         alive = try_candidate(P, B, L, i, v, drv, r, NONE, slo, shi) &&
                 prepare_item(P, B, L, i, v, slo, shi, &drv2, &clo, &chi);
       }
