@@ -210,13 +210,19 @@ wcdl_status wcdl_add_rules_text(wcdl_engine* e, const char* text);
 wcdl_status wcdl_rule_count(const wcdl_engine* e, uint32_t* n);
 
 /* Helper-relation splitting (Sec. 5, the CallGraphEdge rewrite): factor the
- * body atoms atom_idx[0..n) of rule rule_id into a new relation whose columns
+ * body atoms atom_idx[0..n) of rule rule_id into a relation whose columns
  * are the variables those atoms share with the rest of the rule (other
  * atoms, head, comparisons), in order of first occurrence.  The rule becomes
- * head <- remaining atoms, helper(shared...) and a new rule
- * helper(shared...) <- selected atoms is added.  The least model of every
- * previously declared relation is unchanged.  *helper_rel receives the new
- * relation's id (named "<head>__h<k>"). */
+ * head <- remaining atoms, helper(shared...) and a rule
+ * helper(shared...) <- selected atoms is added, carrying the orders among
+ * its columns that the rule's comparisons imply.  Indices refer to the body
+ * as the rule was registered; a later split of the same rule may select
+ * atoms that an earlier one already moved into a helper (a conjunction may
+ * repeat atoms), but not only such atoms.  A helper whose definition equals
+ * an earlier helper's up to variable names is that relation again, with no
+ * new rule.  The least model of every previously declared relation is
+ * unchanged.  *helper_rel receives the helper's relation id (new ones are
+ * named "<head>__h<k>"). */
 wcdl_status wcdl_split_rule(wcdl_engine* e, uint32_t rule_id, const uint32_t* atom_idx,
                             uint32_t n, uint32_t* helper_rel);
 

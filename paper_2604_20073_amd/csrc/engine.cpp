@@ -130,6 +130,10 @@ struct Rule {
   std::vector<Cmp> cmps;
   u32 nvars = 0;
   std::vector<u32> var_order;  // optional user order (original variable ids)
+  // Helper-relation splitting: the body as registered, and where each of its
+  // atoms now sits in `body` (-1 once a split moved it into a helper).
+  std::vector<Atom> orig;
+  std::vector<int> orig_at;
 };
 
 struct Relation {
@@ -228,6 +232,7 @@ struct wcdl_engine {
   std::string err;
   uint64_t* pinned = nullptr;  // host-pinned scratch for device->host scalars
   uint32_t helper_count = 0;
+  std::map<std::string, uint32_t> helper_keys;  // canonical helper definition -> relation
   wcdl_run_stats last{};
   // Rows produced per work unit by each rule version (rule, delta atom) the
   // last time it ran; sizes the count-pass staging arena.
@@ -1788,6 +1793,36 @@ u32 declare(Engine* e, const std::string& name, u32 arity, bool internal = false
 
 using namespace wcdl;
 
+namespace wcdl {
+
+// Canonical text of a helper rule: variables renamed by first occurrence
+// (head, then body, then comparisons); comparisons sorted.  Two helpers with
+// equal keys define the same relation.
+std::string helper_key(const Rule& h) {
+  std::map<u32, u32> ren;
+  auto term = [&](const Term& t) {
+    if (!t.var) return "c" + std::to_string(t.v);
+    auto it = ren.find(t.v);
+    if (it == ren.end()) it = ren.emplace(t.v, (u32)ren.size()).first;
+    return "v" + std::to_string(it->second);
+  };
+  std::string k = "h" + std::to_string(h.head.t.size()) + "(";
+  for (auto& t : h.head.t) k += term(t) + ",";
+  k += "):-";
+  for (auto& a : h.body) {
+    k += std::to_string(a.rel) + "(";
+    for (auto& t : a.t) k += term(t) + ",";
+    k += ")";
+  }
+  std::vector<std::string> cs;
+  for (auto& c : h.cmps) cs.push_back(term(c.a) + "op" + std::to_string((int)c.op) + term(c.b));
+  std::sort(cs.begin(), cs.end());
+  for (auto& c : cs) k += ";" + c;
+  return k;
+}
+
+}  // namespace wcdl
+
 extern "C" {
 
 void wcdl_config_default(wcdl_config* cfg) {
@@ -1948,18 +1983,27 @@ wcdl_status wcdl_split_rule(wcdl_engine* e, uint32_t rule_id, const uint32_t* at
     if (rule_id >= e->rules.size()) throw Error(WCDL_E_INVALID, "unknown rule id");
     if (!atom_idx || n == 0) throw Error(WCDL_E_INVALID, "no atoms selected");
     Rule r = e->rules[rule_id];
-    std::set<u32> sel(atom_idx, atom_idx + n);
+    if (r.orig.empty()) {
+      r.orig = r.body;
+      r.orig_at.resize(r.body.size());
+      for (size_t k = 0; k < r.body.size(); ++k) r.orig_at[k] = (int)k;
+    }
+    std::set<u32> sel(atom_idx, atom_idx + n);  // indices into the registered body
     if (sel.size() != n) throw Error(WCDL_E_INVALID, "repeated atom index");
     for (u32 a : sel)
-      if (a >= r.body.size()) throw Error(WCDL_E_INVALID, "atom index out of range");
-    if (sel.size() >= r.body.size()) throw Error(WCDL_E_INVALID, "must keep at least one atom");
+      if (a >= r.orig.size()) throw Error(WCDL_E_INVALID, "atom index out of range");
+    std::set<u32> present;  // selected atoms still in the body (positions)
+    for (u32 a : sel)
+      if (r.orig_at[a] >= 0) present.insert((u32)r.orig_at[a]);
+    if (present.empty()) throw Error(WCDL_E_INVALID, "every selected atom is already in a helper");
+    if (sel.size() >= r.orig.size()) throw Error(WCDL_E_INVALID, "must keep at least one atom");
     std::set<u32> inner;  // variables of the selected atoms
     for (u32 a : sel)
-      for (auto& t : r.body[a].t)
+      for (auto& t : r.orig[a].t)
         if (t.var) inner.insert(t.v);
     std::set<u32> outer;  // variables used elsewhere
     for (u32 a = 0; a < r.body.size(); ++a)
-      if (!sel.count(a))
+      if (!present.count(a))
         for (auto& t : r.body[a].t)
           if (t.var) outer.insert(t.v);
     for (auto& t : r.head.t)
@@ -2005,37 +2049,57 @@ wcdl_status wcdl_split_rule(wcdl_engine* e, uint32_t rule_id, const uint32_t* at
     }
     std::vector<u32> shared;  // in order of first occurrence in the selected atoms
     for (u32 a : sel)
-      for (auto& t : r.body[a].t)
+      for (auto& t : r.orig[a].t)
         if (t.var && outer.count(t.v) && std::find(shared.begin(), shared.end(), t.v) == shared.end())
           shared.push_back(t.v);
     if (shared.empty()) throw Error(WCDL_E_UNSUPPORTED, "selected atoms share no variable with the rule");
     if (shared.size() > (size_t)MAXA) throw Error(WCDL_E_UNSUPPORTED, "helper relation would exceed arity 6");
-    std::string hname = e->rels[r.head.rel].name + "__h" + std::to_string(e->helper_count);
-    while (e->rel_ids.count(hname)) hname += "_";
     Rule helper, consumer;
     helper.nvars = consumer.nvars = r.nvars;
-    u32 hid = (u32)e->rels.size();
-    helper.head.rel = hid;
     for (u32 v : shared) helper.head.t.push_back(Term{true, v});
-    for (u32 a : sel) helper.body.push_back(r.body[a]);
+    for (u32 a : sel) helper.body.push_back(r.orig[a]);
     helper.cmps = helper_cmps;
+    const std::string key = helper_key(helper);
+    auto known = e->helper_keys.find(key);
+    const bool reuse = known != e->helper_keys.end();
+    std::string hname;
+    u32 hid;
+    if (reuse) {
+      hid = known->second;  // an earlier split defined this very relation
+    } else {
+      hname = e->rels[r.head.rel].name + "__h" + std::to_string(e->helper_count);
+      while (e->rel_ids.count(hname)) hname += "_";
+      hid = (u32)e->rels.size();
+    }
+    helper.head.rel = hid;
     consumer.head = r.head;
+    consumer.orig = r.orig;
+    consumer.orig_at.assign(r.orig.size(), -1);
     for (u32 a = 0; a < r.body.size(); ++a)
-      if (!sel.count(a)) consumer.body.push_back(r.body[a]);
+      if (!present.count(a)) {
+        for (size_t k = 0; k < r.orig.size(); ++k)
+          if (r.orig_at[k] == (int)a) consumer.orig_at[k] = (int)consumer.body.size();
+        consumer.body.push_back(r.body[a]);
+      }
     consumer.body.push_back(helper.head);
     consumer.cmps = rest_cmps;
-    declare(e, hname, (u32)shared.size(), true);
+    if (!reuse) declare(e, hname, (u32)shared.size(), true);
     try {
-      validate_rule(e, helper);
+      if (!reuse) validate_rule(e, helper);
       validate_rule(e, consumer);
     } catch (...) {
-      e->rel_ids.erase(hname);
-      e->rels.pop_back();
+      if (!reuse) {
+        e->rel_ids.erase(hname);
+        e->rels.pop_back();
+      }
       throw;
     }
-    e->helper_count++;
     e->rules[rule_id] = consumer;
-    e->rules.push_back(helper);
+    if (!reuse) {
+      e->helper_count++;
+      e->helper_keys.emplace(key, hid);
+      e->rules.push_back(helper);
+    }
     if (helper_rel) *helper_rel = hid;
   });
 }

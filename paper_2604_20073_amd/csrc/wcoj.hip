@@ -398,34 +398,26 @@ __device__ inline u64 rank_alive(bool alive, WgState& st, u64* tot) {
 
 // One chunk of output candidates, called by every thread: count them
 // (mode 0), write them at their final offsets (mode 1), or count them and
-// stage them in arena chunks (mode 2).  Lane t holds candidates t + k*WG of
+// stage them in arena chunks (mode 2).  Lane t holds candidates t*K + k of
 // the chunk (k < K); rows keep that order, which is traversal order.
 template <int MODE, int K>
 __device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, int L,
-                                  const u32 (&i)[K], const u32 (&v)[K], const bool (&alive)[K],
+                                  const u32 (&i)[K], const u32 (&v)[K], const u32 (&alive)[K],
                                   u64 obase, u64 b, u64& my_count) {
-  static_assert(K * WG <= STAGE_CHUNK && WG < 65536 && K <= 4, "ranks are packed in 16 bits");
-  if (MODE == 0) {
+  static_assert(K * WG <= STAGE_CHUNK, "one call stages at most one new arena chunk");
+  u32 mine = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) my_count += alive[k] ? 1 : 0;
+  for (int k = 0; k < K; ++k) mine += alive[k];
+  if (MODE == 0) {
+    my_count += mine;
     return;
   }
-  // One scan ranks all K sub-chunks: field k (16 bits) counts sub-chunk k.
-  u64 x = 0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) x |= (u64)(alive[k] ? 1 : 0) << (16 * k);
-  u64 tots;
-  const u64 rks = block_excl_scan(x, st.sh, &tots);
-  u64 rk[K], tot = 0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    rk[k] = tot + ((rks >> (16 * k)) & 0xffffu);
-    tot += (tots >> (16 * k)) & 0xffffu;
-  }
+  u64 tot;
+  u64 rk = block_excl_scan(mine, st.sh, &tot);
   if (MODE == 1) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (alive[k]) emit_row(P, B, L, i[k], v[k], obase + st.out + rk[k]);
+      if (alive[k]) emit_row(P, B, L, i[k], v[k], obase + st.out + rk++);
   } else {
     if (threadIdx.x == 0 && !st.ovf && st.out + tot > st.covered) {
       // tot <= K*WG <= STAGE_CHUNK: at most one new chunk per call.
@@ -444,7 +436,7 @@ __device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, in
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (alive[k]) {
-          const u64 r = st.out + rk[k];
+          const u64 r = st.out + rk++;
           const u64 c = st.chunk[(r / STAGE_CHUNK) & 1];
           stage_row(P, B, L, i[k], v[k], c * STAGE_CHUNK + (r % STAGE_CHUNK));
         }
@@ -456,98 +448,108 @@ __device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, in
   __syncthreads();
 }
 
-// Leaf candidates g0 + t + k*WG (lane t, k < K) of buffer bl: the parent
-// item, the value, and whether every source of the leaf level holds it.  The
-// K lookups of a lane proceed in lockstep, so each step has K independent
-// memory reads in flight instead of one.  At the leaf every source's column
-// is its last, so only membership matters: no ranges are narrowed.
+// Leaf candidates g0 + t*K + k (lane t, k < K) of buffer bl: the parent item,
+// the value, and whether every source of the leaf level holds it.  A lane's
+// candidates are consecutive, so one search finds the first one's item and
+// the rest step forward (every item has at least one candidate).  At the
+// leaf every source's column is its last, so only membership matters: no
+// ranges are narrowed.
+//
+// The code is branch-free per candidate: lanes past the end work on the last
+// candidate (every read stays in bounds) and are dropped at the end; reads
+// that a lane does not need go to row 0 of the same column; the K membership
+// searches of a lane advance in lockstep, in a loop that runs while any lane
+// of the wave still searches.  Divergent branches would cost more scalar
+// instructions (execution-mask bookkeeping) than the memory reads they skip.
 template <int K>
 __device__ inline void leaf_probe(const DPlan* P, const Bufs& B, int L, int bl, u32 nb, u64 g0,
-                                  u64 total, u32 (&it)[K], u32 (&v)[K], bool (&alive)[K]) {
+                                  u64 total, u32 (&it)[K], u32 (&v)[K], u32 (&alive)[K]) {
   const DLevel& lv = P->lvl[L];
-  const u64* pre = reinterpret_cast<const u64*>(B.sm + P->off_pre[bl]);
-  u64 g[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    g[k] = g0 + (u64)k * WG + threadIdx.x;
-    alive[k] = g[k] < total;
-    if (!alive[k]) g[k] = total - 1;  // searched like the rest, then dropped
-  }
-  // Owning item: first i with pre[i] > g (the step count depends on nb only,
-  // so the K searches advance together).
-  u32 base[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) base[k] = 0;
-  for (u32 n = nb; n > 1;) {
-    const u32 half = n >> 1;
-#pragma unroll
-    for (int k = 0; k < K; ++k) base[k] = pre[base[k] + half] <= g[k] ? base[k] + half : base[k];
-    n -= half;
-  }
+  const u32 nsrc = uni(lv.nsrc);
+  const u64* pre = reinterpret_cast<const u64*>(B.sm + uni(P->off_pre[bl]));
+  const u32* clo = B.sm + uni(P->off_clo[bl]);
+  const u32* dsel = B.sm + uni(P->off_drv[bl]);
+  const u64 last = total - 1;
+  const u64 gl = g0 + (u64)threadIdx.x * K;
+  u32 i = owner_item(pre, nb, gl < last ? gl : last);
+  u64 pe = pre[i];
+  u64 gb = i ? pre[i ? i - 1 : 0] : 0;
   u32 drv[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const u32 i = base[k] + (pre[base[k]] <= g[k] ? 1u : 0u);
+    const u64 gk = gl + k;
+    alive[k] = gk <= last ? 1u : 0u;
+    const u64 g = gk <= last ? gk : last;
+    const u32 adv = g >= pe ? 1u : 0u;  // at most one item per step
+    i += adv;
+    gb = adv ? pe : gb;
+    pe = pre[i];
     it[k] = i;
-    const u64 gb = i ? pre[i - 1] : 0;
-    const u32 r = B.sm[P->off_clo[bl] + i] + (u32)(g[k] - gb);
-    drv[k] = B.sm[P->off_drv[bl] + i];
-    v[k] = alive[k] ? ldg(source_col(lv, drv[k]) + r) : 0;
+    drv[k] = dsel[i];
+    v[k] = ldg(source_col(lv, drv[k]) + clo[i] + (u32)(g - gb));
   }
-  for (u32 f = 0; f < lv.nne; ++f) {
+  const u32 nne = uni(lv.nne);
+  for (u32 f = 0; f < nne; ++f) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (v[k] == operand(B, lv.ne[f], L, it[k], v[k])) alive[k] = false;
+    for (int k = 0; k < K; ++k) alive[k] &= v[k] != operand(B, lv.ne[f], L, it[k], v[k]) ? 1u : 0u;
   }
-  for (u32 s = 0; s < lv.nsrc; ++s) {
+  for (u32 s = 0; s < nsrc; ++s) {
     const DSource& src = lv.src[s];
-    if (src.alias != NONE) continue;  // same column and range as an earlier source
-    const u32* col = src.col;
-    if (src.dir) {
+    if (uni(src.alias) != NONE) continue;  // same column and range as an earlier source
+    const u32* col = (const u32*)uni((u64)src.col);
+    const u32* dir = (const u32*)uni((u64)src.dir);
+    u32 act[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) act[k] = alive[k] & (drv[k] != s ? 1u : 0u);
+    if (dir) {
+      const u32 dmax = uni(src.dmax);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (alive[k] && drv[k] != s) {
-          if (v[k] > src.dmax || ldg(src.dir + v[k]) >= ldg(src.dir + v[k] + 1)) alive[k] = false;
-        }
+        const u32 x = v[k] < dmax ? v[k] : dmax;
+        const u32 r0 = ldg(dir + x), r1 = ldg(dir + x + 1);
+        const u32 ok = (v[k] <= dmax ? 1u : 0u) & (r0 < r1 ? 1u : 0u);
+        alive[k] &= (act[k] ^ 1u) | ok;
       }
       continue;
     }
-    u32 lo[K], hi[K];
-    bool run[K], found[K];
+    const u32 a = uni(src.atom);
+    const u32 slot = uni(P->atom_slot[L - 1][a]);
+    const u32 cap = uni(P->cap);
+    const u32* slo = slot == NONE ? nullptr : B.sm + uni(P->off_lo[L - 1]) + slot * cap;
+    const u32* shi = slot == NONE ? nullptr : B.sm + uni(P->off_hi[L - 1]) + slot * cap;
+    const u32 r0lo = B.rng0[2 * a], r0hi = B.rng0[2 * a + 1];
+    u32 lo[K], hi[K], run[K], found[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const bool act = alive[k] && drv[k] != s;
-      lo[k] = act ? B.lo(L - 1, src.atom, it[k]) : 0;
-      hi[k] = act ? B.hi(L - 1, src.atom, it[k]) : 0;
-      run[k] = lo[k] < hi[k];
-      found[k] = !act;
+      lo[k] = slo ? slo[it[k]] : r0lo;
+      hi[k] = shi ? shi[it[k]] : r0hi;
+      run[k] = act[k] & (lo[k] < hi[k] ? 1u : 0u);
+      found[k] = act[k] ^ 1u;
     }
     for (;;) {
-      bool any = false;
+      u32 any = 0;
 #pragma unroll
-      for (int k = 0; k < K; ++k) any = any || run[k];
-      if (!any) break;
+      for (int k = 0; k < K; ++k) any |= run[k];
+      if (__ballot(any) == 0) break;
       u32 mid[K], x[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         mid[k] = lo[k] + ((hi[k] - lo[k]) >> 1);
-        x[k] = run[k] ? ldg(col + mid[k]) : 0;
+        x[k] = ldg(col + (run[k] ? mid[k] : 0u));
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (run[k]) {
-          if (x[k] == v[k]) {
-            found[k] = true;
-            run[k] = false;
-          } else {
-            if (x[k] < v[k]) lo[k] = mid[k] + 1; else hi[k] = mid[k];
-            run[k] = lo[k] < hi[k];
-          }
-        }
+        const u32 eq = x[k] == v[k] ? run[k] : 0u;
+        const u32 lt = x[k] < v[k] ? run[k] : 0u;
+        const u32 gt = run[k] & ((eq | lt) ^ 1u);
+        found[k] |= eq;
+        lo[k] = lt ? mid[k] + 1 : lo[k];
+        hi[k] = gt ? mid[k] : hi[k];
+        run[k] &= (eq ^ 1u) & (lo[k] < hi[k] ? 1u : 0u);
       }
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) alive[k] = alive[k] && found[k];
+    for (int k = 0; k < K; ++k) alive[k] &= found[k];
   }
 }
 
@@ -622,8 +624,7 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
           }
         }
         if (m == 1) {
-          const u32 ia[1] = {0}, va[1] = {v};
-          const bool aa[1] = {alive};
+          const u32 ia[1] = {0}, va[1] = {v}, aa[1] = {alive ? 1u : 0u};
           emit_chunk<MODE, 1>(P, B, st, 0, ia, va, aa, obase, b, my_count);
         } else {
           u64 tot;
@@ -661,8 +662,7 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
       }
       const u64 total = uni(st.total[bl]);
       for (u64 g0 = uni(st.cur[bl]); g0 < total; g0 += LEAF_K * WG) {
-        u32 i[LEAF_K], v[LEAF_K];
-        bool alive[LEAF_K];
+        u32 i[LEAF_K], v[LEAF_K], alive[LEAF_K];
         leaf_probe<LEAF_K>(P, B, L, bl, nb, g0, total, i, v, alive);
         emit_chunk<MODE, LEAF_K>(P, B, st, L, i, v, alive, obase, b, my_count);
       }

@@ -437,3 +437,34 @@ def test_split_q_through_ascending_triangles():
     H = e.read_numpy("H")
     assert np.all(H[:, 0] < H[:, 1]) and np.all(H[:, 1] < H[:, 2])  # ascending triangles only
     e.close()
+
+
+def test_split_q_overlapping_helpers_reused():
+    """Two splits of q over overlapping atom sets: {edge(w,x), edge(x,y),
+    edge(w,y)} and {edge(w,x), edge(x,z), edge(w,z)} define the same helper
+    (ascending triangles) up to variable names, so the second split reuses
+    it: q(w,x,y,z) :- T(w,x,y), T(w,x,z), edge(y,z), y < z.  q unchanged."""
+    edges = W.rmat_graph(12, 40000, 56)
+    rules = TRI + "\n" + Q4
+    _, expect = oracle.evaluate({"edge": 2, "tri": 3, "q": 4}, rules, {"edge": edges})
+    e = Engine()
+    for n, k in {"edge": 2, "tri": 3, "q": 4}.items():
+        e.declare(n, k)
+    e.add_rules(rules)
+    h1 = e.split_rule(1, [0, 1, 2])
+    n_rules = e.rule_count()
+    h2 = e.split_rule(1, [0, 4, 5])
+    assert h1 == h2 and e.rule_count() == n_rules  # no second helper rule
+    with pytest.raises(WcdlError):
+        e.split_rule(1, [0])  # already inside the helper
+    e.load("edge", edges)
+    e.run()
+    assert np.array_equal(e.read_numpy("q"), expect["q"])
+    assert np.array_equal(e.read_numpy("tri"), expect["tri"])
+    e.arity["T"] = 3
+    e.ids["T"] = h1
+    T = e.read_numpy("T")
+    tri = expect["tri"]
+    asc = tri[(tri[:, 0] < tri[:, 1]) & (tri[:, 1] < tri[:, 2])]
+    assert np.array_equal(T, asc)
+    e.close()

@@ -296,3 +296,35 @@ def test_helper_split_pointsto_same_model():
         expect = as_sorted_array(points_to(rel["addressOf"], rel["assign"], rel["load"],
                                            rel["store"]), 2)
         assert np.array_equal(split["pt"], expect)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_4clique_through_shared_triangle_helper_same_model(seed):
+    """The overlapping helper split of q (Sec. 5 rewrite, both atom groups
+    define the ascending triangles T) leaves q unchanged: the rewritten
+    program and the rule as written have the same least model on the oracle,
+    and both equal the 4-cliques counted by brute force."""
+    edges = W.rmat_graph(9, 3000, 600 + seed)
+    rewritten = ("T(a,b,c) :- edge(a,b), edge(b,c), edge(a,c), a < b, b < c, a < c.\n"
+                 "q(w,x,y,z) :- edge(y,z), T(w,x,y), T(w,x,z), w < x, x < y, y < z.")
+    _, split = oracle.evaluate({"edge": 2, "T": 3, "q": 4}, rewritten, {"edge": edges})
+    _, plain = oracle.evaluate({"edge": 2, "q": 4}, Q4, {"edge": edges})
+    assert np.array_equal(split["q"], plain["q"])
+    es = {tuple(r) for r in edges.tolist()}
+    nodes = sorted({v for r in es for v in r})
+    adj = {v: set() for v in nodes}
+    for a, b in es:
+        adj[a].add(b)
+    cliques = set()
+    for w in nodes:
+        for x in adj[w]:
+            if x <= w:
+                continue
+            for y in adj[w] & adj[x]:
+                if y <= x:
+                    continue
+                for z in adj[w] & adj[x] & adj[y]:
+                    if z > y:
+                        cliques.add((w, x, y, z))
+    assert np.array_equal(plain["q"], as_sorted_array(cliques, 4))
+    assert len(cliques) > 0
