@@ -526,8 +526,6 @@ std::vector<u32> choose_order(const Rule& r, int delta_atom) {
   return order;
 }
 
-constexpr u32 LDS_BUDGET = 48 * 1024;
-
 // Build a version of rule `ri` with atom `delta_atom` read from the delta (or
 // -1 for none).  Pointers are filled later.
 Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
@@ -740,13 +738,11 @@ Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
     }
     return w;
   };
-  // Keep at least three workgroups resident per CU where possible.
-  u32 cap = 512;
-  u32 words = layout(cap);
-  if (words * 4 > LDS_BUDGET) {
-    cap = 256;
-    words = layout(cap);
-  }
+  // One workgroup's worth of items per buffer: the join is bound by memory
+  // latency, so LDS goes to more resident workgroups rather than to longer
+  // buffers (measured on the triangle join: 17% faster than 512 items).
+  const u32 cap = 256;
+  const u32 words = layout(cap);
   if (words * 4 > 150 * 1024) throw Error(WCDL_E_UNSUPPORTED, "join too deep for LDS; split the rule");
   P.cap = cap;
   P.lds_words = words;

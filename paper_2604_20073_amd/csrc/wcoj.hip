@@ -167,8 +167,11 @@ __device__ inline u32 operand(const Bufs& B, const DOperand& o, int L, u32 i, u3
 // per-lane indexed read of the plan would put a dependent memory access in
 // front of every column read.
 __device__ inline const u32* source_col(const DLevel& lv, u32 s) {
-  const u32* col = (const u32*)uni((u64)lv.src[0].col);
-  for (u32 t = 1; t < lv.nsrc; ++t) {
+  const u32 n = uni(lv.nsrc);
+  const u32* c0 = (const u32*)uni((u64)lv.src[0].col);
+  const u32* c1 = n > 1 ? (const u32*)uni((u64)lv.src[1].col) : c0;
+  const u32* col = s == 1 ? c1 : c0;
+  for (u32 t = 2; t < n; ++t) {
     const u32* c = (const u32*)uni((u64)lv.src[t].col);
     if (s == t) col = c;
   }
@@ -518,38 +521,43 @@ __device__ inline void leaf_probe(const DPlan* P, const Bufs& B, int L, int bl, 
     const u32* slo = slot == NONE ? nullptr : B.sm + uni(P->off_lo[L - 1]) + slot * cap;
     const u32* shi = slot == NONE ? nullptr : B.sm + uni(P->off_hi[L - 1]) + slot * cap;
     const u32 r0lo = B.rng0[2 * a], r0hi = B.rng0[2 * a + 1];
-    u32 lo[K], hi[K], run[K], found[K];
+    // Search [lo, hi) for v: base moves to the last row with value <= v while
+    // the window length halves; xb is the value at base.  Lanes that need no
+    // search get the window [0, 1), row 0 of a column that is not empty.
+    u32 base[K], len[K], xb[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      lo[k] = slo ? slo[it[k]] : r0lo;
-      hi[k] = shi ? shi[it[k]] : r0hi;
-      run[k] = act[k] & (lo[k] < hi[k] ? 1u : 0u);
-      found[k] = act[k] ^ 1u;
+      const u32 lo = slo ? slo[it[k]] : r0lo;
+      const u32 hi = shi ? shi[it[k]] : r0hi;
+      const u32 use = act[k] & (lo < hi ? 1u : 0u);
+      base[k] = use ? lo : 0u;
+      len[k] = use ? hi - lo : 0u;
+      xb[k] = ldg(col + base[k]);
     }
     for (;;) {
-      u32 any = 0;
+      u32 most = len[0];
 #pragma unroll
-      for (int k = 0; k < K; ++k) any |= run[k];
-      if (__ballot(any) == 0) break;
+      for (int k = 1; k < K; ++k) most = most > len[k] ? most : len[k];
+      if (__ballot(most > 1) == 0) break;
       u32 mid[K], x[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        mid[k] = lo[k] + ((hi[k] - lo[k]) >> 1);
-        x[k] = ldg(col + (run[k] ? mid[k] : 0u));
+        mid[k] = base[k] + (len[k] >> 1);
+        x[k] = ldg(col + mid[k]);
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const u32 eq = x[k] == v[k] ? run[k] : 0u;
-        const u32 lt = x[k] < v[k] ? run[k] : 0u;
-        const u32 gt = run[k] & ((eq | lt) ^ 1u);
-        found[k] |= eq;
-        lo[k] = lt ? mid[k] + 1 : lo[k];
-        hi[k] = gt ? mid[k] : hi[k];
-        run[k] &= (eq ^ 1u) & (lo[k] < hi[k] ? 1u : 0u);
+        const bool le = x[k] <= v[k];
+        base[k] = le ? mid[k] : base[k];
+        xb[k] = le ? x[k] : xb[k];
+        len[k] -= len[k] >> 1;
       }
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) alive[k] &= found[k];
+    for (int k = 0; k < K; ++k) {
+      const u32 found = (len[k] != 0 ? 1u : 0u) & (xb[k] == v[k] ? 1u : 0u);
+      alive[k] &= (act[k] ^ 1u) | found;
+    }
   }
 }
 
