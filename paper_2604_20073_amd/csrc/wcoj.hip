@@ -496,43 +496,82 @@ __device__ inline void leaf_probe(const DPlan* P, const Bufs& B, int L, int bl, 
 #pragma unroll
     for (int k = 0; k < K; ++k) alive[k] &= v[k] != operand(B, lv.ne[f], L, it[k], v[k]) ? 1u : 0u;
   }
+  // Sources read through a directory (an unnarrowed first column): two reads.
+  // Aliases repeat an earlier source's column and range and are skipped.
+  u32 nsearch = 0;
+  const u32* col0 = nullptr;  // column of the first searched source
+  u32 dsr[K];                 // the candidate's driver is a searched source
+#pragma unroll
+  for (int k = 0; k < K; ++k) dsr[k] = 0;
   for (u32 s = 0; s < nsrc; ++s) {
     const DSource& src = lv.src[s];
-    if (uni(src.alias) != NONE) continue;  // same column and range as an earlier source
-    const u32* col = (const u32*)uni((u64)src.col);
+    if (uni(src.alias) != NONE) continue;
     const u32* dir = (const u32*)uni((u64)src.dir);
-    u32 act[K];
+    if (!dir) {
+      if (!nsearch) col0 = (const u32*)uni((u64)src.col);
+      ++nsearch;
 #pragma unroll
-    for (int k = 0; k < K; ++k) act[k] = alive[k] & (drv[k] != s ? 1u : 0u);
-    if (dir) {
-      const u32 dmax = uni(src.dmax);
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const u32 x = v[k] < dmax ? v[k] : dmax;
-        const u32 r0 = ldg(dir + x), r1 = ldg(dir + x + 1);
-        const u32 ok = (v[k] <= dmax ? 1u : 0u) & (r0 < r1 ? 1u : 0u);
-        alive[k] &= (act[k] ^ 1u) | ok;
-      }
+      for (int k = 0; k < K; ++k) dsr[k] |= drv[k] == s ? 1u : 0u;
       continue;
     }
-    const u32 a = uni(src.atom);
-    const u32 slot = uni(P->atom_slot[L - 1][a]);
-    const u32 cap = uni(P->cap);
-    const u32* slo = slot == NONE ? nullptr : B.sm + uni(P->off_lo[L - 1]) + slot * cap;
-    const u32* shi = slot == NONE ? nullptr : B.sm + uni(P->off_hi[L - 1]) + slot * cap;
-    const u32 r0lo = B.rng0[2 * a], r0hi = B.rng0[2 * a + 1];
+    const u32 dmax = uni(src.dmax);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const u32 act = alive[k] & (drv[k] != s ? 1u : 0u);
+      const u32 x = v[k] < dmax ? v[k] : dmax;
+      const u32 r0 = ldg(dir + x), r1 = ldg(dir + x + 1);
+      const u32 ok = (v[k] <= dmax ? 1u : 0u) & (r0 < r1 ? 1u : 0u);
+      alive[k] &= (act ^ 1u) | ok;
+    }
+  }
+  // Searched sources, in rounds: in round j each lane searches the j-th
+  // searched source other than its candidate's driver, so a wave whose items
+  // have different drivers still makes one pass per round.
+  // Candidates whose driver is searched need one round fewer; the last
+  // round runs only if some live candidate of the wave has another driver.
+  u32 drv_other = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) drv_other |= alive[k] & (dsr[k] ^ 1u);
+  u32 rounds = nsearch;
+  if (nsearch && __ballot(drv_other) == 0) rounds = nsearch - 1;
+  const u32 cap = uni(P->cap);
+  for (u32 j = 0; j < rounds; ++j) {
+    const u32* tcol[K];
+    u32 lo[K], hi[K], act[K], cnt[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) tcol[k] = col0, lo[k] = 0, hi[k] = 0, act[k] = 0, cnt[k] = 0;
+    for (u32 s = 0; s < nsrc; ++s) {
+      const DSource& src = lv.src[s];
+      if (uni(src.alias) != NONE || uni((u64)src.dir) != 0) continue;
+      const u32* col = (const u32*)uni((u64)src.col);
+      const u32 a = uni(src.atom);
+      const u32 slot = uni(P->atom_slot[L - 1][a]);
+      const u32* slo = slot == NONE ? nullptr : B.sm + uni(P->off_lo[L - 1]) + slot * cap;
+      const u32* shi = slot == NONE ? nullptr : B.sm + uni(P->off_hi[L - 1]) + slot * cap;
+      const u32 r0lo = B.rng0[2 * a], r0hi = B.rng0[2 * a + 1];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const u32 other = drv[k] != s ? 1u : 0u;
+        const bool pick = other && cnt[k] == j;
+        const u32 l = slo ? slo[it[k]] : r0lo;
+        const u32 h = shi ? shi[it[k]] : r0hi;
+        tcol[k] = pick ? col : tcol[k];
+        lo[k] = pick ? l : lo[k];
+        hi[k] = pick ? h : hi[k];
+        act[k] |= pick ? 1u : 0u;
+        cnt[k] += other;
+      }
+    }
     // Search [lo, hi) for v: base moves to the last row with value <= v while
-    // the window length halves; xb is the value at base.  Lanes that need no
-    // search get the window [0, 1), row 0 of a column that is not empty.
+    // the window length halves; xb is the value at base.  Lanes with nothing
+    // to search get the window [0, 0) of a column that is not empty.
     u32 base[K], len[K], xb[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const u32 lo = slo ? slo[it[k]] : r0lo;
-      const u32 hi = shi ? shi[it[k]] : r0hi;
-      const u32 use = act[k] & (lo < hi ? 1u : 0u);
-      base[k] = use ? lo : 0u;
-      len[k] = use ? hi - lo : 0u;
-      xb[k] = ldg(col + base[k]);
+      const u32 use = alive[k] & act[k] & (lo[k] < hi[k] ? 1u : 0u);
+      base[k] = use ? lo[k] : 0u;
+      len[k] = use ? hi[k] - lo[k] : 0u;
+      xb[k] = ldg(tcol[k] + base[k]);
     }
     for (;;) {
       u32 most = len[0];
@@ -543,7 +582,7 @@ __device__ inline void leaf_probe(const DPlan* P, const Bufs& B, int L, int bl, 
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         mid[k] = base[k] + (len[k] >> 1);
-        x[k] = ldg(col + mid[k]);
+        x[k] = ldg(tcol[k] + mid[k]);
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
