@@ -40,23 +40,31 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def profiled_traffic(kernel: str, scale: int, edges: int):
+def kernel_source_digest() -> str:
+    """First 16 hex digits of the SHA-256 of the join kernel and its planner."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("wcoj.hip", "engine.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_2604_20073_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None if it was taken on other kernel source or another
     workload."""
-    import hashlib
     import re
 
     path = os.path.join(ROOT, "profiles", "hbm_traffic_k_join_rmat20_tri_q4.md")
-    src = os.path.join(ROOT, "paper_2604_20073_amd", "csrc", "wcoj.hip")
-    if not (os.path.exists(path) and scale == 20 and edges == 1 << 24):
+    if not os.path.exists(path):
         return None
     m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
     if not m:
         return None
     rec = json.loads(m.group(1))
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if rec.get("wcoj_hip_sha256_16") != digest or not kernel.startswith(rec.get("kernel", "?")):
+    if (rec.get("source_sha256_16") != kernel_source_digest() or rec.get("workload") != workload
+            or not kernel.startswith(rec.get("kernel", "?"))):
         return None
     return int(rec["traffic_bytes_per_launch"])
 
@@ -402,6 +410,7 @@ def main():
     derived = n_tri + n_q
     value = derived / (ms_per_step / 1000.0)
 
+    traffic_key = f"rmat-{args.scale} {args.edges} edges tri+q4" + (" split" if args.split else "")
     # Dominant kernel: the join kernel that traverses the work space and
     # produces the rows (the staged count pass when staging is on, else the
     # materialize pass).  Algorithmic bytes per launch: every candidate value
@@ -418,7 +427,7 @@ def main():
     achieved = (alg_bytes / (kms / 1000.0)) / 1e9 if kms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": profiled_traffic(kname, args.scale, args.edges),
+                "traffic": profiled_traffic(kname, traffic_key),
                 "kernel": kname, "avg_launch_ms": round(kms / max(launches, 1), 3),
                 "bytes_per_launch": int(alg_bytes / max(launches, 1))}
     phases = {k: round(sum(s["phase_ms"][k] for s in stats) / args.steps, 2)
