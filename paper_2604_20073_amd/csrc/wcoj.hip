@@ -32,6 +32,9 @@ namespace {
 
 constexpr int WG = 256;
 constexpr int LEAF_K = 4;  // leaf candidates per lane and step
+constexpr int XP_RPT = 8;                         // cross-product rows per thread
+constexpr u32 XP_ROWS = (u32)WG * XP_RPT;         // rows per cross-product workgroup
+constexpr u32 XP_KEYS = 1024;                     // root keys cached per workgroup
 constexpr u32 UMAX = 0xffffffffu;
 
 // Reads of device columns through the global address space.  The column
@@ -826,50 +829,96 @@ __global__ __launch_bounds__(WG) void k_hist(const DPlan* __restrict__ P, RootSp
 // of Sec. 5): local = g - C[key-1], then mixed-radix digits over the levels.
 __global__ __launch_bounds__(WG) void k_xprod(const DPlan* __restrict__ P, RootSpace rs,
                                               const u32* klo, const u32* kd, u64 g0, u64 g1) {
-  __shared__ u64 kr[2];
-  const u64 ub = g0 + (u64)blockIdx.x * WG;
-  const u64 ue = ub + WG < g1 ? ub + WG : g1;
+  // A workgroup writes XP_ROWS consecutive rows, XP_RPT per thread (strided
+  // by WG, so every store instruction is coalesced).  The inclusive work
+  // prefix of the root keys it covers is cached in LDS, so finding a row's
+  // key is an LDS search; the rows of a thread are decoded level by level
+  // together, so their loads are independent and in flight at once.  A head
+  // column is written as soon as its level's value is known.
+  __shared__ u64 kend[XP_KEYS];
+  __shared__ u64 kr[3];
+  const u64 ub = g0 + (u64)blockIdx.x * XP_ROWS;
+  const u64 ue = ub + XP_ROWS < g1 ? ub + XP_ROWS : g1;
   if (threadIdx.x == 0) {
-    u64 k0 = owner_key(rs.C, 0, rs.K, ub);
+    const u64 k0 = owner_key(rs.C, 0, rs.K, ub);
     kr[0] = k0;
     kr[1] = owner_key(rs.C, k0, rs.K, ue - 1) + 1;
+    kr[2] = k0 ? ldg(rs.C + k0 - 1) : 0;
   }
   __syncthreads();
-  const u64 g = ub + threadIdx.x;
-  if (g >= g1) return;
-  if (g >= P->out_rows) {
-    atomicOr(P->err, 1u);
-    return;
-  }
-  const u64 kk = owner_key(rs.C, kr[0], kr[1], g);
-  u64 local = g - (kk ? rs.C[kk - 1] : 0);
-  u32 vals[MAXV];
-  vals[0] = rs.U[kk];
-  for (int j = (int)P->m - 1; j >= 1; --j) {
-    const u32 d = kd[(u64)j * rs.K + kk];
-    u32 ij;
-    if (local <= 0xffffffffull) {
-      u32 l32 = (u32)local;
-      ij = l32 % d;
-      local = l32 / d;
+  const u64 k0 = kr[0], k1 = kr[1], s0 = kr[2];
+  const u32 nk = (u32)(k1 - k0);
+  const bool cached = k1 - k0 <= XP_KEYS;
+  if (cached)
+    for (u32 i = threadIdx.x; i < nk; i += WG) kend[i] = ldg(rs.C + k0 + i);
+  __syncthreads();
+  const u32 m = uni(P->m), ha = uni(P->head_arity);
+  const u64 K = rs.K;
+  u64 g[XP_RPT], kk[XP_RPT], local[XP_RPT];
+  u32 ok[XP_RPT];
+  u32 bad = 0;
+#pragma unroll
+  for (int r = 0; r < XP_RPT; ++r) {
+    const u64 gr = ub + (u64)r * WG + threadIdx.x;
+    ok[r] = gr < ue ? 1u : 0u;
+    bad |= ok[r] & (gr >= P->out_rows ? 1u : 0u);  // never when count and write agree
+    ok[r] &= gr < P->out_rows ? 1u : 0u;
+    g[r] = gr < ue ? gr : ue - 1;
+    u64 start;
+    if (cached) {
+      // First i with kend[i] > g (kend[nk-1] >= ue > g).
+      u32 lo = 0, n = nk;
+      while (n > 1) {
+        const u32 half = n >> 1;
+        lo = kend[lo + half - 1] <= g[r] ? lo + half : lo;
+        n -= half;
+      }
+      kk[r] = k0 + lo;
+      start = lo ? kend[lo - 1] : s0;
     } else {
-      ij = (u32)(local % d);
-      local /= d;
+      kk[r] = owner_key(rs.C, k0, k1, g[r]);
+      start = kk[r] ? ldg(rs.C + kk[r] - 1) : 0;
     }
-    const u32 x = P->lvl[j].src[0].col[klo[(u64)j * rs.K + kk] + ij];
-#pragma unroll
-    for (int t = 1; t < MAXV; ++t)
-      if (t == j) vals[t] = x;
+    local[r] = g[r] - start;
   }
-  for (u32 h = 0; h < P->head_arity; ++h) {
-    const DOperand& o = P->head[h];
-    u32 x = o.v;
-    if (o.is_var) {
+  if (bad) atomicOr(P->err, 1u);
+  // Head columns that are constants or the root variable.
+  for (u32 h = 0; h < ha; ++h) {
+    const DOperand o = P->head[h];
+    u32* out = P->out[h];
+    if (o.is_var && o.v != 0) continue;
 #pragma unroll
-      for (int t = 0; t < MAXV; ++t)
-        if ((u32)t == o.v) x = vals[t];
+    for (int r = 0; r < XP_RPT; ++r) {
+      const u32 x = o.is_var ? ldg(rs.U + kk[r]) : o.v;
+      if (ok[r]) out[g[r]] = x;
     }
-    P->out[h][g] = x;
+  }
+  for (u32 j = m - 1; j >= 1; --j) {
+    const u32* col = (const u32*)uni((u64)P->lvl[j].src[0].col);
+    u32 x[XP_RPT];
+#pragma unroll
+    for (int r = 0; r < XP_RPT; ++r) {
+      const u32 d = ldg(kd + (u64)j * K + kk[r]);
+      const u32 base = ldg(klo + (u64)j * K + kk[r]);
+      u32 ij;
+      if (local[r] <= 0xffffffffull) {
+        const u32 l32 = (u32)local[r];
+        ij = l32 % d;
+        local[r] = l32 / d;
+      } else {
+        ij = (u32)(local[r] % d);
+        local[r] /= d;
+      }
+      x[r] = ldg(col + base + ij);
+    }
+    for (u32 h = 0; h < ha; ++h) {
+      const DOperand o = P->head[h];
+      if (!o.is_var || o.v != j) continue;
+      u32* out = P->out[h];
+#pragma unroll
+      for (int r = 0; r < XP_RPT; ++r)
+        if (ok[r]) out[g[r]] = x[r];
+    }
   }
 }
 
@@ -1011,7 +1060,9 @@ void join_xprod(Ctx c, const DPlan* d_plan, const RootSpace& rs, const u32* klo,
                 u32 m, u64 g0, u64 g1) {
   (void)m;
   if (g1 <= g0) return;
-  k_xprod<<<grid1(g1 - g0), WG, 0, c.s>>>(d_plan, rs, klo, kd, g0, g1);
+  const u64 nwg = ceil_div(g1 - g0, (u64)XP_ROWS);
+  if (nwg > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "grid too large");
+  k_xprod<<<(u32)nwg, WG, 0, c.s>>>(d_plan, rs, klo, kd, g0, g1);
   WCDL_HIP(hipGetLastError());
 }
 
