@@ -360,14 +360,20 @@ struct WgState {
   u32 n[MAXV];        // items in each level buffer
   u64 total[MAXV];    // candidates of each level buffer
   u64 cur[MAXV];      // candidates consumed
-  u64 out;            // rows counted / written so far
   u64 key_next;       // next root key to turn into a level-0 item
   u64 exam[MAXV];     // candidates examined by this workgroup, per level
   u32 rng0[2 * MAXN];
   u64 sh[WG / 64];
-  u64 covered;        // staged rows for which chunks are held
-  u64 chunk[2];       // arena chunks holding the current and next row ranges
-  u32 ovf;            // staging arena exhausted for this workgroup
+  u64 alloc;          // arena chunk just taken (broadcast to the workgroup)
+};
+
+// Output state of a workgroup, held in registers by every thread (all
+// threads see the same chunk totals, so they update it identically).
+struct Emit {
+  u64 out = 0;        // rows written / staged so far
+  u64 covered = 0;    // staged rows for which arena chunks are held
+  u64 chunk0 = 0, chunk1 = 0;  // arena chunks of even / odd 4096-row ranges
+  u32 ovf = 0;        // staging arena exhausted for this workgroup
 };
 
 // Inclusive prefix of candidate counts of buffer b; sets total, resets cursor.
@@ -405,9 +411,11 @@ __device__ inline u64 rank_alive(bool alive, WgState& st, u64* tot) {
 // One chunk of output candidates, called by every thread: count them
 // (mode 0), write them at their final offsets (mode 1), or count them and
 // stage them in arena chunks (mode 2).  Lane t holds candidates t*K + k of
-// the chunk (k < K); rows keep that order, which is traversal order.
+// the chunk (k < K); rows keep that order, which is traversal order.  Only
+// the rank scan synchronises the workgroup (plus one barrier when a new
+// arena chunk is taken): the output state lives in every thread's registers.
 template <int MODE, int K>
-__device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, int L,
+__device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, Emit& em, int L,
                                   const u32 (&i)[K], const u32 (&v)[K], const u32 (&alive)[K],
                                   u64 obase, u64 b, u64& my_count) {
   static_assert(K * WG <= STAGE_CHUNK, "one call stages at most one new arena chunk");
@@ -420,38 +428,41 @@ __device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, in
   }
   u64 tot;
   u64 rk = block_excl_scan(mine, st.sh, &tot);
+  tot = uni(tot);
   if (MODE == 1) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (alive[k]) emit_row(P, B, L, i[k], v[k], obase + st.out + rk++);
+      if (alive[k]) emit_row(P, B, L, i[k], v[k], obase + em.out + rk++);
   } else {
-    if (threadIdx.x == 0 && !st.ovf && st.out + tot > st.covered) {
+    if (!em.ovf && em.out + tot > em.covered) {
       // tot <= K*WG <= STAGE_CHUNK: at most one new chunk per call.
-      const u64 c = atomicAdd(reinterpret_cast<unsigned long long*>(P->stage_next), 1ull);
+      const u64 seq = em.covered / STAGE_CHUNK;
+      if (threadIdx.x == 0) {
+        const u64 c = atomicAdd(reinterpret_cast<unsigned long long*>(P->stage_next), 1ull);
+        if (c < P->stage_chunks) P->chunk_tag[c] = (b << 32) | seq;
+        st.alloc = c;
+      }
+      __syncthreads();
+      const u64 c = uni(st.alloc);
       if (c >= P->stage_chunks) {
-        st.ovf = 1;
+        em.ovf = 1;
       } else {
-        const u64 seq = st.covered / STAGE_CHUNK;
-        P->chunk_tag[c] = (b << 32) | seq;
-        st.chunk[seq & 1] = c;
-        st.covered += STAGE_CHUNK;
+        if (seq & 1) em.chunk1 = c; else em.chunk0 = c;
+        em.covered += STAGE_CHUNK;
       }
     }
-    __syncthreads();
-    if (!st.ovf) {
+    if (!em.ovf) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (alive[k]) {
-          const u64 r = st.out + rk++;
-          const u64 c = st.chunk[(r / STAGE_CHUNK) & 1];
+          const u64 r = em.out + rk++;
+          const u64 c = ((r / STAGE_CHUNK) & 1) ? em.chunk1 : em.chunk0;
           stage_row(P, B, L, i[k], v[k], c * STAGE_CHUNK + (r % STAGE_CHUNK));
         }
       }
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) st.out += tot;
-  __syncthreads();
+  em.out += tot;
 }
 
 // Leaf candidates g0 + t*K + k (lane t, k < K) of buffer bl: the parent item,
@@ -629,9 +640,6 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
   const u64 klast = owner_key(rs.C, kfirst, rs.K, ue - 1);
   if (threadIdx.x == 0) {
     st.key_next = kfirst;
-    st.out = 0;
-    st.covered = 0;
-    st.ovf = 0;
     for (int j = 0; j < MAXV; ++j) st.exam[j] = 0;
     st.exam[0] = klast - kfirst + 1;
     for (int j = 0; j < MAXV; ++j) st.n[j] = 0, st.total[j] = 0, st.cur[j] = 0;
@@ -640,6 +648,7 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
   Bufs B{sm, P, st.rng0};
   const u64 obase = MODE == 1 ? offsets[b] : 0;
   u64 my_count = 0;  // leaf rows found by this lane (count mode)
+  Emit em;
   int bl = -1;       // buffer being drained; -1 = root keys
 
   for (;;) {
@@ -675,7 +684,7 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
         }
         if (m == 1) {
           const u32 ia[1] = {0}, va[1] = {v}, aa[1] = {alive ? 1u : 0u};
-          emit_chunk<MODE, 1>(P, B, st, 0, ia, va, aa, obase, b, my_count);
+          emit_chunk<MODE, 1>(P, B, st, em, 0, ia, va, aa, obase, b, my_count);
         } else {
           u64 tot;
           u64 rk = rank_alive(alive, st, &tot);
@@ -714,7 +723,7 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
       for (u64 g0 = uni(st.cur[bl]); g0 < total; g0 += LEAF_K * WG) {
         u32 i[LEAF_K], v[LEAF_K], alive[LEAF_K];
         leaf_probe<LEAF_K>(P, B, L, bl, nb, g0, total, i, v, alive);
-        emit_chunk<MODE, LEAF_K>(P, B, st, L, i, v, alive, obase, b, my_count);
+        emit_chunk<MODE, LEAF_K>(P, B, st, em, L, i, v, alive, obase, b, my_count);
       }
       if (threadIdx.x == 0) st.cur[bl] = total;
       __syncthreads();
@@ -759,8 +768,8 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
     if (threadIdx.x == 0) counts[b] = tot;
   } else if (MODE == 2) {
     if (threadIdx.x == 0) {
-      counts[b] = st.out;
-      P->ovf[b] = st.ovf;
+      counts[b] = em.out;
+      P->ovf[b] = em.ovf;
     }
   }
   if (MODE != 0 && P->cand && threadIdx.x < P->m)
