@@ -72,6 +72,10 @@ typedef int32_t wcdl_status;
                                     decode); use the general kernel instead */
 #define WCDL_F_STAGE_OFF 0x8u    /* never stage rows during the count pass: the
                                     write pass always re-runs the traversal */
+#define WCDL_F_HEAD_BODY_OFF 0x20u /* merge every round's delta straight into the
+                                    full relation instead of into a small head
+                                    run that is flushed into the body past a
+                                    size ratio (Sec. 4, Merge) */
 #define WCDL_F_BATCHED 0x10u     /* batched mode: the engine holds many independent
                                     instances of one program.  Every relation gets
                                     an implicit leading column, the instance id:

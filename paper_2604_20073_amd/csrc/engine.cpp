@@ -141,7 +141,11 @@ struct Relation {
   u32 arity = 0;        // stored columns (the instance column included in batched mode)
   u32 user_arity = 0;   // columns as declared
   Cols base;                                   // loaded facts, canonical order
-  Cols full;                                   // current relation, canonical order
+  Cols full;                                   // current relation (the body), canonical order
+  // Rows merged this stratum but not yet into `full` (Sec. 4, Merge): the
+  // relation is full ∪ head, disjoint.  Only kept while no join of the
+  // stratum reads the full relation; empty outside a stratum's rounds.
+  Cols head;
   std::map<std::vector<u32>, Cols> full_ord;   // other column orders of full
   std::map<std::vector<u32>, Cols> delta_ord;  // current delta, by column order
   std::vector<u64> delta_sizes;
@@ -337,7 +341,8 @@ Cols empty_cols(u32 k, const std::vector<u32>& order) {
 }
 
 // rows(a) \ rows(b), both sorted unique in the same order.
-Cols difference(Engine* e, size_t si, const Cols& a, const Cols& b) {
+// a \ b \ b2 (b2 optional) for sorted-unique runs in the same order.
+Cols difference(Engine* e, size_t si, const Cols& a, const Cols& b, const Cols* b2 = nullptr) {
   Cols out;
   out.order = a.order;
   const u32 k = a.arity();
@@ -351,7 +356,10 @@ Cols difference(Engine* e, size_t si, const Cols& a, const Cols& b) {
     op.push_back(out.col.back().get());
   }
   auto ap = a.ptrs(), bp = b.ptrs();
-  out.n = set_difference(ctx(e, si), k, ap.data(), a.n, bp.data(), b.n, op.data());
+  std::vector<const u32*> b2p;
+  if (b2 && b2->n) b2p = b2->ptrs();
+  out.n = set_difference(ctx(e, si), k, ap.data(), a.n, bp.data(), b.n, op.data(),
+                         b2p.empty() ? nullptr : b2p.data(), b2p.empty() ? 0 : b2->n);
   return out;
 }
 
@@ -858,12 +866,15 @@ void ensure_directory(Engine* e, Cols& c) {
   build_directory(ctx(e), c.col[0].get(), c.n, vmax, c.dir.get());
 }
 
+void flush_head(Engine* e, u32 rel, Stats* st);
+
 // The sorted copy of (relation, delta?, order) a version reads; built on
 // demand from the canonical copy.
 Cols& get_cols(Engine* e, u32 rel, bool delta, const std::vector<u32>& order) {
   Relation& R = e->rels[rel];
   const std::vector<u32> canon = canonical(R.arity);
   if (!delta) {
+    if (R.head.n) flush_head(e, rel, nullptr);  // joins read one sorted run
     if (order == canon) return R.full;
     auto it = R.full_ord.find(order);
     if (it == R.full_ord.end()) it = R.full_ord.emplace(order, reorder(e, 0, R.full, order)).first;
@@ -1384,7 +1395,7 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
 void absorb_chunk(Engine* e, u32 rel, Cols&& rows, bool presorted, Cols& acc, Stats& st) {
   Relation& R = e->rels[rel];
   auto t = Clock::now();
-  if (presorted && R.full.n == 0) {
+  if (presorted && R.full.n == 0 && R.head.n == 0) {
     // Ascending disjoint chunks: nothing to sort or subtract.
     if (acc.n == 0) acc = std::move(rows);
     else if (rows.n) acc = merged(e, 0, acc, rows);
@@ -1392,7 +1403,7 @@ void absorb_chunk(Engine* e, u32 rel, Cols&& rows, bool presorted, Cols& acc, St
     Cols srt = sort_rows(e, 0, rows.order, std::vector<const u32*>(rows.ptrs()), rows.n, true);
     rows = Cols();
     recycle(e);
-    Cols d = difference(e, 0, srt, R.full);
+    Cols d = difference(e, 0, srt, R.full, &R.head);
     srt = Cols();
     recycle(e);
     if (acc.n == 0) {
@@ -1406,11 +1417,45 @@ void absorb_chunk(Engine* e, u32 rel, Cols&& rows, bool presorted, Cols& acc, St
   st.phase[WCDL_PH_DELTA] += ms_since(t);
 }
 
-// Merge the new rows into full and into every other maintained column order
-// of full (Merge, Sec. 4).
-void commit_delta(Engine* e, u32 rel, Cols& d, Stats& st, bool consume = false) {
+// Merge the head run into the body and into every other maintained column
+// order of it.
+void flush_head(Engine* e, u32 rel, Stats* st) {
+  Relation& R = e->rels[rel];
+  if (R.head.n == 0) return;
+  auto t = Clock::now();
+  Cols h = std::move(R.head);
+  R.head = empty_cols(R.arity, canonical(R.arity));
+  if (R.full.n == 0) {
+    R.full = std::move(h);
+    for (auto& kv : R.full_ord) kv.second = reorder(e, 0, R.full, kv.first);
+  } else {
+    R.full = merged(e, 0, R.full, h);
+    for (auto& kv : R.full_ord) kv.second = merged(e, 0, kv.second, reorder(e, 0, h, kv.first));
+  }
+  WCDL_HIP(hipStreamSynchronize(e->streams[0]));
+  if (st) st->phase[WCDL_PH_MERGE] += ms_since(t);
+}
+
+// Head runs are flushed once they hold more than this share of the body.
+constexpr u64 HEAD_RATIO = 8;
+constexpr u64 HEAD_MIN_ROWS = 1u << 16;
+
+// Merge the new rows into the relation (Merge, Sec. 4).  With `use_head`
+// they go into the small head run, which is flushed into the body (and its
+// other column orders) only past a share of the body's size, so a long tail
+// of small deltas does not rewrite the body every round; otherwise straight
+// into full and every other maintained column order of it.
+void commit_delta(Engine* e, u32 rel, Cols& d, Stats& st, bool consume = false,
+                  bool use_head = false) {
   Relation& R = e->rels[rel];
   auto t = Clock::now();
+  if (d.n && use_head && R.full.n) {
+    R.head = R.head.n == 0 ? copy_cols(e, d) : merged(e, 0, R.head, d);
+    WCDL_HIP(hipStreamSynchronize(e->streams[0]));
+    st.phase[WCDL_PH_MERGE] += ms_since(t);
+    if (R.head.n > std::max<u64>(HEAD_MIN_ROWS, R.full.n / HEAD_RATIO)) flush_head(e, rel, &st);
+    return;
+  }
   if (d.n) {
     if (R.full.n == 0) {
       // `consume`: the caller no longer needs d, so it becomes full as is.
@@ -1444,6 +1489,7 @@ void run_program(Engine* e, wcdl_run_stats* stats_out) {
   Stats st;
   for (auto& R : e->rels) {
     R.full = copy_cols(e, R.base);
+    R.head = empty_cols(R.arity, canonical(R.arity));
     R.full_ord.clear();
     R.delta_ord.clear();
     R.delta_sizes.clear();
@@ -1492,6 +1538,13 @@ void run_program(Engine* e, wcdl_run_stats* stats_out) {
         if (in.count(r.body[j].rel)) vs.push_back(plan_version(e, ri, (int)j, e->cfg.flags));
     }
     for (auto& v : vs) v.sorted_output = false;
+    // Relations of the stratum whose full copy no version joins get a head
+    // run (their full copy only serves to tell new rows from known ones).
+    std::set<u32> joined_full;
+    for (auto& v : vs)
+      for (auto& a : v.atoms)
+        if (!a.delta && in.count(a.rel)) joined_full.insert(a.rel);
+    const bool head_body = !(e->cfg.flags & WCDL_F_HEAD_BODY_OFF);
     for (;;) {
       auto fresh = new_rows(e, vs, st);
       std::map<u32, Cols> nd;
@@ -1500,7 +1553,7 @@ void run_program(Engine* e, wcdl_run_stats* stats_out) {
         auto it = fresh.find(rel);
         Cols d = it != fresh.end() ? std::move(it->second)
                                    : empty_cols(e->rels[rel].arity, canonical(e->rels[rel].arity));
-        commit_delta(e, rel, d, st);
+        commit_delta(e, rel, d, st, false, head_body && !joined_full.count(rel));
         if (d.n) any = true;
         nd.emplace(rel, std::move(d));
       }
@@ -1514,7 +1567,10 @@ void run_program(Engine* e, wcdl_run_stats* stats_out) {
       sync_all(e);
       if (!any) break;
     }
-    for (u32 rel : comp) e->rels[rel].delta_ord.clear();
+    for (u32 rel : comp) {
+      e->rels[rel].delta_ord.clear();
+      flush_head(e, rel, &st);
+    }
   }
   sync_all(e);
   wcdl_run_stats s{};
@@ -2107,6 +2163,7 @@ wcdl_status wcdl_run(wcdl_engine* e, wcdl_run_stats* stats) {
 wcdl_status wcdl_relation_size(const wcdl_engine* ce, uint32_t rel, uint64_t* n_rows) {
   auto* e = const_cast<wcdl_engine*>(ce);
   return guarded(e, [&] {
+    if (rel < e->rels.size() && e->rels[rel].head.n) flush_head(e, rel, nullptr);
     if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
     if (!n_rows) throw Error(WCDL_E_INVALID, "null argument");
     const Relation& R = e->rels[rel];
@@ -2118,6 +2175,7 @@ wcdl_status wcdl_read_columns(const wcdl_engine* ce, uint32_t rel, uint32_t* con
                               uint64_t capacity, uint64_t* n_written, int on_device) {
   auto* e = const_cast<wcdl_engine*>(ce);
   return guarded(e, [&] {
+    if (rel < e->rels.size() && e->rels[rel].head.n) flush_head(e, rel, nullptr);
     if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
     const Relation& R = e->rels[rel];
     const Cols& src = R.full.n ? R.full : R.base;
@@ -2149,6 +2207,7 @@ wcdl_status wcdl_relation_range(const wcdl_engine* ce, uint32_t rel, uint32_t le
                                 uint64_t* first, uint64_t* count) {
   auto* e = const_cast<wcdl_engine*>(ce);
   return guarded(e, [&] {
+    if (rel < e->rels.size() && e->rels[rel].head.n) flush_head(e, rel, nullptr);
     if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
     const Relation& R = e->rels[rel];
     const Cols& src = R.full.n ? R.full : R.base;
@@ -2168,6 +2227,7 @@ wcdl_status wcdl_read_rows(const wcdl_engine* ce, uint32_t rel, uint64_t first, 
                            uint32_t* const* cols_out, int on_device) {
   auto* e = const_cast<wcdl_engine*>(ce);
   return guarded(e, [&] {
+    if (rel < e->rels.size() && e->rels[rel].head.n) flush_head(e, rel, nullptr);
     if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
     const Relation& R = e->rels[rel];
     const Cols& src = R.full.n ? R.full : R.base;

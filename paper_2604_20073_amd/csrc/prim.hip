@@ -351,42 +351,107 @@ __global__ __launch_bounds__(WG) void k_compact(ColsIn a, ColsOut o, u32 k, u64 
   for (u32 j = 0; j < k; ++j) o.c[j][p] = a.c[j][i];
 }
 
-__global__ __launch_bounds__(WG) void k_absent_flags(ColsIn a, ColsIn b, u32 k, u64 na, u64 nb,
-                                                     u32* flags) {
-  __shared__ u64 win[2];
-  const u64 t0 = (u64)blockIdx.x * SEARCH_TILE;
-  const u64 t1 = (t0 + SEARCH_TILE < na) ? t0 + SEARCH_TILE : na;
-  if (threadIdx.x == 0) tile_window(a, b, k, t0, t1, nb, &win[0], &win[1]);
-  __syncthreads();
-  const u64 wlo = win[0], whi = win[1];
-  for (u64 i = t0 + threadIdx.x; i < t1; i += WG) {
-    u32 key[MAXA];
-    load_row(a, k, i, key);
-    u64 p = row_lower_bound(b, k, wlo, whi, key);
-    flags[i] = (p < whi && row_equal(b, k, p, key)) ? 0u : 1u;
-  }
-}
-
-// Each row of `a` goes to its own index plus the number of rows of `b`
-// below it (runs are disjoint, so that count is exact).
-__global__ __launch_bounds__(WG) void k_merge_place(ColsIn a, ColsIn b, ColsOut o, u32 k, u64 na,
-                                                    u64 nb) {
-  __shared__ u64 win[2];
+// flags[i] = 1 if row i of `a` is in neither b nor c (c may be empty).
+__global__ __launch_bounds__(WG) void k_absent_flags(ColsIn a, ColsIn b, ColsIn c, u32 k, u64 na,
+                                                     u64 nb, u64 nc, u32* flags) {
+  __shared__ u64 win[4];
   const u64 t0 = (u64)blockIdx.x * SEARCH_TILE;
   const u64 t1 = (t0 + SEARCH_TILE < na) ? t0 + SEARCH_TILE : na;
   if (threadIdx.x == 0) {
     if (nb) tile_window(a, b, k, t0, t1, nb, &win[0], &win[1]);
     else win[0] = win[1] = 0;
+  } else if (threadIdx.x == 64) {
+    if (nc) tile_window(a, c, k, t0, t1, nc, &win[2], &win[3]);
+    else win[2] = win[3] = 0;
   }
   __syncthreads();
-  const u64 wlo = win[0], whi = win[1];
+  const u64 blo = win[0], bhi = win[1], clo = win[2], chi = win[3];
   for (u64 i = t0 + threadIdx.x; i < t1; i += WG) {
     u32 key[MAXA];
     load_row(a, k, i, key);
-    u64 p = i + row_lower_bound(b, k, wlo, whi, key);
+    const u64 p = row_lower_bound(b, k, blo, bhi, key);
+    const u64 q = row_lower_bound(c, k, clo, chi, key);
+    const bool in_b = p < bhi && row_equal(b, k, p, key);
+    const bool in_c = q < chi && row_equal(c, k, q, key);
+    flags[i] = (in_b || in_c) ? 0u : 1u;
+  }
+}
+
+// ---- merge path --------------------------------------------------------------
+//
+// The merge of two disjoint sorted runs a, b is cut into output tiles of
+// MP_TILE rows.  A first kernel finds, for every tile boundary d, how many of
+// the first d merged rows come from a (a binary search along the diagonal
+// i + j = d).  A workgroup then stages its tile's slices of a and b in LDS,
+// each thread finds its own sub-diagonal there and merges MP_PT rows into a
+// permutation, and the columns are written out coalesced.
+
+constexpr u32 MP_PT = 8;
+constexpr u32 MP_TILE = WG * MP_PT;  // 2048 output rows per workgroup
+
+__device__ inline bool row_lt_ab(const ColsIn& a, u64 i, const ColsIn& b, u64 j, u32 k) {
 #pragma unroll
-    for (int j = 0; j < MAXA; ++j)
-      if (j < (int)k) o.c[j][p] = key[j];
+  for (int c = 0; c < MAXA; ++c) {
+    if (c < (int)k) {
+      const u32 x = a.c[c][i], y = b.c[c][j];
+      if (x != y) return x < y;
+    }
+  }
+  return false;
+}
+
+// split[t] = rows of a among the first min(t*MP_TILE, na+nb) merged rows.
+__global__ __launch_bounds__(WG) void k_merge_split(ColsIn a, ColsIn b, u32 k, u64 na, u64 nb,
+                                                    u64 nsplit, u64* split) {
+  const u64 t = (u64)blockIdx.x * WG + threadIdx.x;
+  if (t >= nsplit) return;
+  const u64 d = t * MP_TILE < na + nb ? t * MP_TILE : na + nb;
+  u64 lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const u64 mid = lo + ((hi - lo) >> 1);
+    if (row_lt_ab(a, mid, b, d - 1 - mid, k)) lo = mid + 1; else hi = mid;
+  }
+  split[t] = lo;
+}
+
+__global__ __launch_bounds__(WG) void k_merge_tile(ColsIn a, ColsIn b, ColsOut o, u32 k, u64 na,
+                                                   u64 nb, const u64* split) {
+  extern __shared__ __align__(16) u32 msm[];  // k columns of MP_TILE rows, then the permutation
+  u32* perm = msm + (u64)k * MP_TILE;
+  const u64 t = blockIdx.x;
+  const u64 d0 = t * MP_TILE, d1 = d0 + MP_TILE < na + nb ? d0 + MP_TILE : na + nb;
+  const u64 i0 = split[t], i1 = split[t + 1];
+  const u32 nA = (u32)(i1 - i0), n = (u32)(d1 - d0), nB = n - nA;
+  const u64 j0 = d0 - i0;
+  for (u32 c = 0; c < k; ++c) {
+    u32* col = msm + (u64)c * MP_TILE;
+    for (u32 r = threadIdx.x; r < n; r += WG) col[r] = r < nA ? a.c[c][i0 + r] : b.c[c][j0 + r - nA];
+  }
+  __syncthreads();
+  // Row x of the tile's a-part vs row y of its b-part (y indexes the b-part).
+  auto less_ab = [&](u32 x, u32 y) {
+    for (u32 c = 0; c < k; ++c) {
+      const u32 u = msm[(u64)c * MP_TILE + x], v = msm[(u64)c * MP_TILE + nA + y];
+      if (u != v) return u < v;
+    }
+    return false;
+  };
+  const u32 ld = threadIdx.x * MP_PT < n ? threadIdx.x * MP_PT : n;
+  u32 lo = ld > nB ? ld - nB : 0, hi = ld < nA ? ld : nA;
+  while (lo < hi) {
+    const u32 mid = (lo + hi) >> 1;
+    if (less_ab(mid, ld - 1 - mid)) lo = mid + 1; else hi = mid;
+  }
+  u32 ia = lo, ib = ld - lo;
+  for (u32 e = 0; e < MP_PT && ld + e < n; ++e) {
+    const bool take_a = ib >= nB || (ia < nA && less_ab(ia, ib));
+    perm[ld + e] = take_a ? ia++ : nA + ib++;
+  }
+  __syncthreads();
+  for (u32 c = 0; c < k; ++c) {
+    const u32* col = msm + (u64)c * MP_TILE;
+    u32* dst = o.c[c] + d0;
+    for (u32 r = threadIdx.x; r < n; r += WG) dst[r] = col[perm[r]];
   }
 }
 
@@ -535,16 +600,17 @@ u64 unique_rows(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32* const* out_
 }
 
 u64 set_difference(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* b, u64 nb,
-                   u32* const* out) {
+                   u32* const* out, const u32* const* b2, u64 nb2) {
   if (na == 0) return 0;
   ColsIn A = cols_in(k, a);
-  if (nb == 0) {
+  if (nb == 0 && nb2 == 0) {
     for (u32 j = 0; j < k; ++j) copy_u32(c, out[j], a[j], na);
     return na;
   }
   DBuf<u32> flags(c.mem, na);
   DBuf<u64> pos(c.mem, na), total(c.mem, 1);
-  k_absent_flags<<<grid_for(na, SEARCH_TILE), WG, 0, c.s>>>(A, cols_in(k, b), k, na, nb,
+  const ColsIn B = nb ? cols_in(k, b) : ColsIn{}, B2 = nb2 ? cols_in(k, b2) : ColsIn{};
+  k_absent_flags<<<grid_for(na, SEARCH_TILE), WG, 0, c.s>>>(A, B, B2, k, na, nb, nb2,
                                                             flags.get());
   WCDL_HIP(hipGetLastError());
   scan_u32_excl(c, flags.get(), pos.get(), na, total.get());
@@ -558,16 +624,23 @@ u64 set_difference(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* 
 
 void merge_disjoint(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* b, u64 nb,
                     u32* const* out) {
+  if (na + nb == 0) return;
   ColsIn A = cols_in(k, a), B = cols_in(k, b);
   ColsOut O = cols_out(k, out);
-  if (na) {
-    k_merge_place<<<grid_for(na, SEARCH_TILE), WG, 0, c.s>>>(A, B, O, k, na, nb);
-    WCDL_HIP(hipGetLastError());
+  if (na == 0 || nb == 0) {
+    for (u32 j = 0; j < k; ++j) copy_u32(c, out[j], na ? a[j] : b[j], na ? na : nb);
+    return;
   }
-  if (nb) {
-    k_merge_place<<<grid_for(nb, SEARCH_TILE), WG, 0, c.s>>>(B, A, O, k, nb, na);
-    WCDL_HIP(hipGetLastError());
-  }
+  const u64 ntiles = ceil_div(na + nb, (u64)MP_TILE);
+  if (ntiles > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "merge too large");
+  DBuf<u64> split(c.mem, ntiles + 1);
+  k_merge_split<<<grid_for(ntiles + 1, WG), WG, 0, c.s>>>(A, B, k, na, nb, ntiles + 1, split.get());
+  WCDL_HIP(hipGetLastError());
+  const size_t lds = (size_t)(k + 1) * MP_TILE * sizeof(u32);
+  WCDL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_merge_tile),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  k_merge_tile<<<(u32)ntiles, WG, lds, c.s>>>(A, B, O, k, na, nb, split.get());
+  WCDL_HIP(hipGetLastError());
 }
 
 }  // namespace wcdl

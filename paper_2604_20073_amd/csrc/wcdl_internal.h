@@ -253,9 +253,10 @@ void column_or(Ctx c, u32 k, const u32* const* cols, u64 n, u32* d_or);
 
 // Unique adjacent rows of a sorted input; returns the count (synchronises).
 u64 unique_rows(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32* const* out_cols);
-// Rows of sorted-unique A absent from sorted-unique B; returns count (syncs).
+// Rows of sorted-unique A absent from sorted-unique B and from the optional
+// sorted-unique B2; returns count (syncs).
 u64 set_difference(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* b, u64 nb,
-                   u32* const* out);
+                   u32* const* out, const u32* const* b2 = nullptr, u64 nb2 = 0);
 // Merge two disjoint sorted-unique runs into out (na + nb rows).
 void merge_disjoint(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* b, u64 nb,
                     u32* const* out);

@@ -10,8 +10,8 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2604_20073_amd import (WCDL_F_BALANCE_OFF, WCDL_F_STAGE_OFF, WCDL_F_STREAMS_OFF,
-                                  WCDL_F_XPROD_OFF, Engine, WcdlError)
+from paper_2604_20073_amd import (WCDL_F_BALANCE_OFF, WCDL_F_HEAD_BODY_OFF, WCDL_F_STAGE_OFF,
+                                  WCDL_F_STREAMS_OFF, WCDL_F_XPROD_OFF, Engine, WcdlError)
 from paper_2604_20073_amd import workloads as W
 from tests.checkers import render
 from tests.test_oracle_pins import ANDERSEN, ARITY, C4, PROGRAMS, Q4, TC, TRI
@@ -120,7 +120,7 @@ def test_andersen_small():
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("flags", [WCDL_F_BALANCE_OFF, WCDL_F_STREAMS_OFF, WCDL_F_XPROD_OFF,
-                                   WCDL_F_STAGE_OFF,
+                                   WCDL_F_STAGE_OFF, WCDL_F_HEAD_BODY_OFF,
                                    WCDL_F_BALANCE_OFF | WCDL_F_STREAMS_OFF | WCDL_F_XPROD_OFF])
 def test_flags_do_not_change_results(flags):
     edges = W.rmat_graph(10, 6000, 31)
@@ -468,3 +468,31 @@ def test_split_q_overlapping_helpers_reused():
     asc = tri[(tri[:, 0] < tri[:, 1]) & (tri[:, 1] < tri[:, 2])]
     assert np.array_equal(T, asc)
     e.close()
+
+
+SG = ("sg(x,y) :- par(p,x), par(p,y), x != y.\n"
+      "sg(x,y) :- par(a,x), sg(a,b), par(b,y).")
+
+
+@pytest.mark.parametrize("flags", [0, WCDL_F_HEAD_BODY_OFF])
+def test_same_generation_long_tail_head_runs(flags):
+    """Same generation (the paper's linear-recursion benchmark shape) on a
+    deep random tree: hundreds of rounds with small deltas.  sg's full copy
+    is never joined, so its new rows go into a head run that is flushed
+    into the body past a size ratio; results and per-round deltas equal the
+    oracle's with and without head runs."""
+    rng = np.random.default_rng(77)
+    # 20 chains of 300 nodes below the root (sg reaches depth 300, one level
+    # per round) plus 2,000 leaves hung below random nodes.
+    edges, nid = [], 1
+    for _ in range(20):
+        prev = 0
+        for _ in range(300):
+            edges.append((prev, nid))
+            prev, nid = nid, nid + 1
+    for _ in range(2000):
+        edges.append((int(rng.integers(0, nid)), nid))
+        nid += 1
+    par = np.array(edges, dtype=np.uint32)
+    got, stats = check_parity({"par": 2, "sg": 2}, SG, {"par": par}, flags=flags)
+    assert stats["rounds"] > 300 and len(got["sg"]) > 200000
