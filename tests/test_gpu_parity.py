@@ -496,3 +496,18 @@ def test_same_generation_long_tail_head_runs(flags):
     par = np.array(edges, dtype=np.uint32)
     got, stats = check_parity({"par": 2, "sg": 2}, SG, {"par": par}, flags=flags)
     assert stats["rounds"] > 300 and len(got["sg"]) > 200000
+
+
+def test_merge_path_six_columns_many_tiles():
+    """A recursive rule over a 6-column relation: every round merges
+    thousands of new rows into the relation (merge-path tiles of 2,048 rows
+    at the widest row, plus ties across tile boundaries in the difference)."""
+    rng = np.random.default_rng(91)
+    n = 3000
+    nxt = np.stack([np.arange(n - 1, dtype=np.uint32), np.arange(1, n, dtype=np.uint32)], axis=1)
+    seed = rng.integers(0, 50, size=(4000, 6)).astype(np.uint32)
+    seed[:, 0] = rng.integers(0, 40, size=4000).astype(np.uint32)
+    rules = ("w(a,b,c,d,e,f) :- s(a,b,c,d,e,f).\n"
+             "w(a2,b,c,d,e,f) :- w(a,b,c,d,e,f), nxt(a,a2), a < 60.")
+    got, stats = check_parity({"s": 6, "nxt": 2, "w": 6}, rules, {"s": seed, "nxt": nxt})
+    assert len(got["w"]) > 50000 and stats["rounds"] > 10
