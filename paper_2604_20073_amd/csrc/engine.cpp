@@ -866,6 +866,30 @@ void ensure_directory(Engine* e, Cols& c) {
   build_directory(ctx(e), c.col[0].get(), c.n, vmax, c.dir.get());
 }
 
+// Run bitmaps of a copy that leaf levels probe (see Cols).  Built once per
+// copy; only for copies that stay unchanged while they are read.
+constexpr u32 RUN_BITMAP_MIN = 512;
+
+void ensure_run_bitmaps(Engine* e, Cols& c) {
+  if (c.bm_tried || c.n < RUN_BITMAP_MIN || c.arity() < 2) return;
+  c.bm_tried = true;
+  const u32 k = c.arity();
+  // Upper bound of the last column: the OR of its values.
+  DBuf<u32> d_or(e->mem.get(), 1);
+  const u32* last = c.col[k - 1].get();
+  column_or(ctx(e), 1, &last, c.n, d_or.get());
+  u32 orv = 0;
+  WCDL_HIP(hipMemcpyAsync(&orv, d_or.get(), sizeof(u32), hipMemcpyDeviceToHost, e->streams[0]));
+  WCDL_HIP(hipStreamSynchronize(e->streams[0]));
+  const u32 vmax = orv == 0 ? 0 : (orv >= 0x80000000u ? 0xffffffffu : (2u << (31 - __builtin_clz(orv))) - 1);
+  size_t free_b = 0, total_b = 0;
+  WCDL_HIP(hipMemGetInfo(&free_b, &total_b));
+  const u64 budget = std::min<u64>((u64)(total_b * 0.02), (u64)(free_b / 8));
+  auto cp = c.ptrs();
+  c.bm_min = build_run_bitmaps(ctx(e), k, cp.data(), c.n, vmax, RUN_BITMAP_MIN, budget, &c.bm_at,
+                               &c.bm, &c.bm_words);
+}
+
 void flush_head(Engine* e, u32 rel, Stats* st);
 
 // The sorted copy of (relation, delta?, order) a version reads; built on
@@ -1012,6 +1036,24 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     for (u32 L = 0; L < P.m && !R.skip; ++L)
       for (u32 s2 = 0; s2 < P.lvl[L].nsrc; ++s2) {
         DSource& src = P.lvl[L].src[s2];
+        src.bm_at = src.bm = nullptr;
+        src.bm_words = src.bm_min = 0;
+        if (L + 1 == P.m && L > 0 && src.alias == NONE && !v.want_dir[L][s2] && !e->serving) {
+          // Leaf sources of copies that no version of this batch writes.
+          const AtomUse& u = v.atoms[src.atom];
+          bool stable = !u.delta;
+          for (auto& w : vs) stable = stable && w.head_rel != u.rel;
+          if (stable) {
+            Cols& cc = get_cols(e, u.rel, false, u.order);
+            ensure_run_bitmaps(e, cc);
+            if (cc.bm_min) {
+              src.bm_at = cc.bm_at.get();
+              src.bm = cc.bm.get();
+              src.bm_words = cc.bm_words;
+              src.bm_min = cc.bm_min;
+            }
+          }
+        }
         src.dir = nullptr;
         if (!v.want_dir[L][s2]) continue;
         const AtomUse& u = v.atoms[src.atom];

@@ -112,6 +112,13 @@ struct Cols {
   DBuf<u32> dir;       // dense directory of column 0 (built on demand)
   u32 dir_max = 0;
   bool dir_tried = false;
+  // Run bitmaps (built on demand): for every run of rows sharing all but the
+  // last column that is at least bm_min rows long, a bitmap of the last
+  // column's values; bm_at[start row of such a run] = its bitmap, else NONE.
+  DBuf<u32> bm_at, bm;
+  u32 bm_words = 0;    // 32-bit words per bitmap
+  u32 bm_min = 0;      // shortest run with a bitmap (0: none built)
+  bool bm_tried = false;
   u32 arity() const { return (u32)order.size(); }
   std::vector<const u32*> ptrs() const {
     std::vector<const u32*> v;
@@ -147,6 +154,10 @@ struct DSource {      // an atom constraining the level's variable
   u32 last;           // 1 if no variable column of the atom follows
   u32 alias;          // earlier source at this level with the same column and
                       // the same current range (its result is reused), or NONE
+  const u32* bm_at;   // optional run bitmaps of the copy (leaf sources): per
+  const u32* bm;      //   row, the bitmap of the run starting there or NONE
+  u32 bm_words;       // 32-bit words per bitmap
+  u32 bm_min;         // runs shorter than this have no bitmap
 };
 
 struct DBound {       // x_level >= opnd + adj (lo) or x_level <= opnd - adj (hi)
@@ -296,6 +307,13 @@ void join_stage_copy(Ctx c, const DPlan* d_plan, u64 used_chunks, const u64* cou
                      const u64* offsets, u32 arity, u64 w0, u64 w1);
 // Dense directory of a sorted column with values <= vmax: dir[v] = first row
 // with value >= v, for v in [0, vmax+1] (vmax + 2 entries).
+// Run bitmaps of a sorted copy with k >= 2 columns (see Cols): runs of at
+// least `min_run` rows sharing columns 0..k-2 get a bitmap of column k-1's
+// values (vmax: an upper bound of those values), at most max_bytes in
+// total (min_run is raised until they fit).  Returns the shortest run with
+// a bitmap, 0 if none was built (synchronises).
+u32 build_run_bitmaps(Ctx c, u32 k, const u32* const* cols, u64 n, u32 vmax, u32 min_run,
+                      u64 max_bytes, DBuf<u32>* bm_at, DBuf<u32>* bm, u32* words);
 void build_directory(Ctx c, const u32* col, u64 n, u32 vmax, u32* dir);
 // Cross-product decode path: writes the rows of units [g0, g1) (row g = unit g).
 void join_xprod(Ctx c, const DPlan* d_plan, const RootSpace& rs, const u32* klo, const u32* kd,

@@ -181,6 +181,28 @@ __device__ inline const u32* source_col(const DLevel& lv, u32 s) {
   return col;
 }
 
+// Run bitmaps of source s of a level (s varies per lane; the level does not),
+// selected among the sources' wave-uniform fields.
+__device__ inline void source_bitmaps(const DLevel& lv, u32 s, const u32** bm_at, const u32** bm,
+                                      u32* words, u32* bmin) {
+  const u32 n = uni(lv.nsrc);
+  *bm_at = nullptr;
+  *bm = nullptr;
+  *words = 0;
+  *bmin = 0;
+  for (u32 t = 0; t < n; ++t) {
+    const u32* a = (const u32*)uni((u64)lv.src[t].bm_at);
+    const u32* b = (const u32*)uni((u64)lv.src[t].bm);
+    const u32 w = uni(lv.src[t].bm_words), m = uni(lv.src[t].bm_min);
+    if (s == t) {
+      *bm_at = a;
+      *bm = b;
+      *words = w;
+      *bmin = m;
+    }
+  }
+}
+
 // Item of a level buffer owning candidate g: the first i with pre[i] > g,
 // pre being the inclusive prefix of the items' candidate counts (g < pre[n-1]).
 // The number of steps depends on n only.
@@ -551,9 +573,10 @@ __device__ inline void leaf_probe(const DPlan* P, const Bufs& B, int L, int bl, 
   const u32 cap = uni(P->cap);
   for (u32 j = 0; j < rounds; ++j) {
     const u32* tcol[K];
-    u32 lo[K], hi[K], act[K], cnt[K];
+    u32 lo[K], hi[K], act[K], cnt[K], tsrc[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) tcol[k] = col0, lo[k] = 0, hi[k] = 0, act[k] = 0, cnt[k] = 0;
+    for (int k = 0; k < K; ++k)
+      tcol[k] = col0, lo[k] = 0, hi[k] = 0, act[k] = 0, cnt[k] = 0, tsrc[k] = 0;
     for (u32 s = 0; s < nsrc; ++s) {
       const DSource& src = lv.src[s];
       if (uni(src.alias) != NONE || uni((u64)src.dir) != 0) continue;
@@ -570,6 +593,7 @@ __device__ inline void leaf_probe(const DPlan* P, const Bufs& B, int L, int bl, 
         const u32 l = slo ? slo[it[k]] : r0lo;
         const u32 h = shi ? shi[it[k]] : r0hi;
         tcol[k] = pick ? col : tcol[k];
+        tsrc[k] = pick ? s : tsrc[k];
         lo[k] = pick ? l : lo[k];
         hi[k] = pick ? h : hi[k];
         act[k] |= pick ? 1u : 0u;
@@ -579,12 +603,27 @@ __device__ inline void leaf_probe(const DPlan* P, const Bufs& B, int L, int bl, 
     // Search [lo, hi) for v: base moves to the last row with value <= v while
     // the window length halves; xb is the value at base.  Lanes with nothing
     // to search get the window [0, 0) of a column that is not empty.
-    u32 base[K], len[K], xb[K];
+    //
+    // A window that is a run with a bitmap (a run of at least bm_min rows
+    // sharing all but the last column) is answered by one bit instead.
+    u32 base[K], len[K], xb[K], hasb[K], fb[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const u32 use = alive[k] & act[k] & (lo[k] < hi[k] ? 1u : 0u);
-      base[k] = use ? lo[k] : 0u;
-      len[k] = use ? hi[k] - lo[k] : 0u;
+      const u32* bm_at;
+      const u32* bm;
+      u32 words, bmin;
+      source_bitmaps(lv, tsrc[k], &bm_at, &bm, &words, &bmin);
+      const bool try_bm = use && bmin && hi[k] - lo[k] >= bmin;
+      // Reads that are not needed go to row 0 of the (non-empty) column.
+      const u32 bid = ldg(try_bm ? bm_at + lo[k] : tcol[k]);
+      const bool inr = (v[k] >> 5) < words;
+      const bool hb = try_bm && bid != NONE;
+      const u32 word = ldg((hb && inr) ? bm + (u64)bid * words + (v[k] >> 5) : tcol[k]);
+      hasb[k] = hb ? 1u : 0u;
+      fb[k] = (hb && inr && ((word >> (v[k] & 31u)) & 1u)) ? 1u : 0u;
+      base[k] = (use && !hb) ? lo[k] : 0u;
+      len[k] = (use && !hb) ? hi[k] - lo[k] : 0u;
       xb[k] = ldg(tcol[k] + base[k]);
     }
     for (;;) {
@@ -608,7 +647,7 @@ __device__ inline void leaf_probe(const DPlan* P, const Bufs& B, int L, int bl, 
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const u32 found = (len[k] != 0 ? 1u : 0u) & (xb[k] == v[k] ? 1u : 0u);
+      const u32 found = hasb[k] ? fb[k] : (len[k] != 0 ? 1u : 0u) & (xb[k] == v[k] ? 1u : 0u);
       alive[k] &= (act[k] ^ 1u) | found;
     }
   }
@@ -991,6 +1030,65 @@ u32 grid1(u64 n) {
   return (u32)(g ? g : 1);
 }
 
+// ---- run bitmaps ------------------------------------------------------------
+
+struct Prefix { const u32* c[MAXA]; };
+
+// flags[i] = 1 where row i starts a run (differs from row i-1 in columns
+// 0..kp-1).
+__global__ __launch_bounds__(WG) void k_run_flags(Prefix p, u32 kp, u64 n, u32* flags) {
+  const u64 i = (u64)blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  u32 f = i == 0 ? 1u : 0u;
+  for (u32 j = 0; j < kp && !f; ++j) f = p.c[j][i] != p.c[j][i - 1] ? 1u : 0u;
+  flags[i] = f;
+}
+
+// S[pos[i]] = i for every run start i.
+__global__ __launch_bounds__(WG) void k_run_starts(const u32* flags, const u64* pos, u64 n, u32* S) {
+  const u64 i = (u64)blockIdx.x * WG + threadIdx.x;
+  if (i < n && flags[i]) S[pos[i]] = (u32)i;
+}
+
+// hist[b] = number of runs whose length has b as its highest set bit.
+__global__ __launch_bounds__(WG) void k_run_loghist(const u32* S, u64 nruns, u64 n, u32* hist) {
+  const u64 r = (u64)blockIdx.x * WG + threadIdx.x;
+  if (r >= nruns) return;
+  const u64 len = (r + 1 < nruns ? (u64)S[r + 1] : n) - S[r];
+  atomicAdd(&hist[63 - __clzll(len)], 1u);
+}
+
+__global__ __launch_bounds__(WG) void k_run_select(const u32* S, u64 nruns, u64 n, u32 min_run,
+                                                   u32* sel) {
+  const u64 r = (u64)blockIdx.x * WG + threadIdx.x;
+  if (r >= nruns) return;
+  const u64 len = (r + 1 < nruns ? (u64)S[r + 1] : n) - S[r];
+  sel[r] = len >= min_run ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(WG) void k_run_mark(const u32* S, u64 nruns, u64 n, const u32* sel,
+                                                 const u64* ids, u32* bm_at, u32* start,
+                                                 u32* len) {
+  const u64 r = (u64)blockIdx.x * WG + threadIdx.x;
+  if (r >= nruns || !sel[r]) return;
+  const u64 id = ids[r];
+  bm_at[S[r]] = (u32)id;
+  start[id] = S[r];
+  len[id] = (u32)((r + 1 < nruns ? (u64)S[r + 1] : n) - S[r]);
+}
+
+// One workgroup per selected run: set the bits of its last-column values.
+__global__ __launch_bounds__(WG) void k_run_bits(const u32* last, const u32* start,
+                                                 const u32* len, u32 words, u32* bm) {
+  const u64 id = blockIdx.x;
+  const u64 s0 = start[id], l = len[id];
+  u32* b = bm + id * words;
+  for (u64 t = threadIdx.x; t < l; t += WG) {
+    const u32 v = last[s0 + t];
+    atomicOr(&b[v >> 5], 1u << (v & 31u));
+  }
+}
+
 }  // namespace
 
 void join_init_ranges(Ctx c, const DPlan* d_plan, u32 natoms, u32* d_rng0) {
@@ -1024,6 +1122,63 @@ void build_directory(Ctx c, const u32* col, u64 n, u32 vmax, u32* dir) {
   if (n == 0) return;
   k_build_dir<<<grid1((u64)vmax + 2), WG, 0, c.s>>>(col, n, vmax, dir);
   WCDL_HIP(hipGetLastError());
+}
+
+u32 build_run_bitmaps(Ctx c, u32 k, const u32* const* cols, u64 n, u32 vmax, u32 min_run,
+                      u64 max_bytes, DBuf<u32>* bm_at, DBuf<u32>* bm, u32* words) {
+  if (k < 2 || k > (u32)MAXA || n < min_run || n >= 0xffffffffull) return 0;
+  Prefix p{};
+  for (u32 j = 0; j + 1 < k; ++j) p.c[j] = cols[j];
+  DBuf<u32> flags(c.mem, n);
+  DBuf<u64> pos(c.mem, n), tot(c.mem, 1);
+  k_run_flags<<<grid1(n), WG, 0, c.s>>>(p, k - 1, n, flags.get());
+  WCDL_HIP(hipGetLastError());
+  scan_u32_excl(c, flags.get(), pos.get(), n, tot.get());
+  u64 nruns = 0;
+  WCDL_HIP(hipMemcpyAsync(&nruns, tot.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
+  WCDL_HIP(hipStreamSynchronize(c.s));
+  DBuf<u32> S(c.mem, nruns);
+  k_run_starts<<<grid1(n), WG, 0, c.s>>>(flags.get(), pos.get(), n, S.get());
+  WCDL_HIP(hipGetLastError());
+  DBuf<u32> hist(c.mem, 64);
+  fill_u32(c, hist.get(), 64, 0);
+  k_run_loghist<<<grid1(nruns), WG, 0, c.s>>>(S.get(), nruns, n, hist.get());
+  WCDL_HIP(hipGetLastError());
+  u32 h[64];
+  WCDL_HIP(hipMemcpyAsync(h, hist.get(), sizeof(h), hipMemcpyDeviceToHost, c.s));
+  WCDL_HIP(hipStreamSynchronize(c.s));
+  const u64 w = ((u64)vmax >> 5) + 1;
+  // Raise the threshold (a power of two) until the bitmaps fit.
+  u32 b0 = 0;
+  while ((1u << b0) < min_run) ++b0;
+  u64 nsel = 0;
+  for (;; ++b0) {
+    if (b0 >= 32) return 0;
+    nsel = 0;
+    for (u32 b = b0; b < 64; ++b) nsel += h[b];
+    if (nsel == 0) return 0;
+    if (nsel * w * 4 + n * 4 <= max_bytes) break;
+  }
+  const u32 thr = 1u << b0;
+  DBuf<u32> sel(c.mem, nruns);
+  DBuf<u64> ids(c.mem, nruns);
+  k_run_select<<<grid1(nruns), WG, 0, c.s>>>(S.get(), nruns, n, thr, sel.get());
+  WCDL_HIP(hipGetLastError());
+  scan_u32_excl(c, sel.get(), ids.get(), nruns, nullptr);
+  *bm_at = DBuf<u32>(c.mem, n);
+  *bm = DBuf<u32>(c.mem, nsel * w);
+  fill_u32(c, bm_at->get(), n, NONE);
+  fill_u32(c, bm->get(), nsel * w, 0);
+  DBuf<u32> st(c.mem, nsel), ln(c.mem, nsel);
+  k_run_mark<<<grid1(nruns), WG, 0, c.s>>>(S.get(), nruns, n, sel.get(), ids.get(), bm_at->get(),
+                                          st.get(), ln.get());
+  WCDL_HIP(hipGetLastError());
+  if (nsel > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "too many run bitmaps");
+  k_run_bits<<<(u32)nsel, WG, 0, c.s>>>(cols[k - 1], st.get(), ln.get(), (u32)w, bm->get());
+  WCDL_HIP(hipGetLastError());
+  WCDL_HIP(hipStreamSynchronize(c.s));
+  *words = (u32)w;
+  return thr;
 }
 
 void join_histogram(Ctx c, const DPlan* d_plan, const RootSpace& rs, u64* W, u32* klo, u32* kd,
