@@ -25,6 +25,9 @@
 // workgroup's rows at its offset in traversal order, so the output is
 // deterministic and, in variable order, lexicographically sorted.
 
+#include <algorithm>
+#include <functional>
+
 #include "wcdl_internal.h"
 
 namespace wcdl {
@@ -1034,47 +1037,64 @@ u32 grid1(u64 n) {
 
 struct Prefix { const u32* c[MAXA]; };
 
-// flags[i] = 1 where row i starts a run (differs from row i-1 in columns
-// 0..kp-1).
-__global__ __launch_bounds__(WG) void k_run_flags(Prefix p, u32 kp, u64 n, u32* flags) {
-  const u64 i = (u64)blockIdx.x * WG + threadIdx.x;
-  if (i >= n) return;
-  u32 f = i == 0 ? 1u : 0u;
-  for (u32 j = 0; j < kp && !f; ++j) f = p.c[j][i] != p.c[j][i - 1] ? 1u : 0u;
-  flags[i] = f;
+__device__ inline int prefix_cmp(const Prefix& p, u32 kp, u64 i, u64 j) {
+  for (u32 c = 0; c < kp; ++c) {
+    const u32 x = p.c[c][i], y = p.c[c][j];
+    if (x != y) return x < y ? -1 : 1;
+  }
+  return 0;
 }
 
-// S[pos[i]] = i for every run start i.
-__global__ __launch_bounds__(WG) void k_run_starts(const u32* flags, const u64* pos, u64 n, u32* S) {
-  const u64 i = (u64)blockIdx.x * WG + threadIdx.x;
-  if (i < n && flags[i]) S[pos[i]] = (u32)i;
+// Long runs without reading every row: a run of at least 2*RUN_PROBE rows
+// holds two probe rows j and j + RUN_PROBE (j a multiple of RUN_PROBE) with
+// equal prefixes.  Such a probe finds the run's bounds by binary search and
+// reports it once, from the first probe row inside it.
+constexpr u32 RUN_PROBE = 256;
+
+__global__ __launch_bounds__(WG) void k_run_probe(Prefix p, u32 kp, u64 n, u32 min_run,
+                                                  u32* count, u32 cap, u32* rs, u32* re) {
+  const u64 t = (u64)blockIdx.x * WG + threadIdx.x;
+  const u64 j = t * RUN_PROBE;
+  if (j + RUN_PROBE >= n || prefix_cmp(p, kp, j, j + RUN_PROBE) != 0) return;
+  // First row of the run: lower bound of row j's prefix in [0, j].
+  u64 lo = 0, hi = j;
+  while (lo < hi) {
+    const u64 mid = lo + ((hi - lo) >> 1);
+    if (prefix_cmp(p, kp, mid, j) < 0) lo = mid + 1; else hi = mid;
+  }
+  const u64 s = lo;
+  if ((s + RUN_PROBE - 1) / RUN_PROBE * RUN_PROBE != j) return;  // not the run's first probe
+  // End of the run: upper bound in [j + RUN_PROBE, n).
+  lo = j + RUN_PROBE;
+  hi = n;
+  while (lo < hi) {
+    const u64 mid = lo + ((hi - lo) >> 1);
+    if (prefix_cmp(p, kp, mid, j) <= 0) lo = mid + 1; else hi = mid;
+  }
+  if (lo - s < min_run) return;
+  const u32 at = atomicAdd(count, 1u);
+  if (at < cap) {
+    rs[at] = (u32)s;
+    re[at] = (u32)lo;
+  }
 }
 
-// hist[b] = number of runs whose length has b as its highest set bit.
-__global__ __launch_bounds__(WG) void k_run_loghist(const u32* S, u64 nruns, u64 n, u32* hist) {
-  const u64 r = (u64)blockIdx.x * WG + threadIdx.x;
-  if (r >= nruns) return;
-  const u64 len = (r + 1 < nruns ? (u64)S[r + 1] : n) - S[r];
-  atomicAdd(&hist[63 - __clzll(len)], 1u);
+// Bitmap ids for the runs kept (length >= thr, in list order).
+__global__ __launch_bounds__(WG) void k_run_keep(const u32* rs, const u32* re, u32 nruns, u32 thr,
+                                                 u32* keep) {
+  const u32 r = blockIdx.x * WG + threadIdx.x;
+  if (r < nruns) keep[r] = re[r] - rs[r] >= thr ? 1u : 0u;
 }
 
-__global__ __launch_bounds__(WG) void k_run_select(const u32* S, u64 nruns, u64 n, u32 min_run,
-                                                   u32* sel) {
-  const u64 r = (u64)blockIdx.x * WG + threadIdx.x;
-  if (r >= nruns) return;
-  const u64 len = (r + 1 < nruns ? (u64)S[r + 1] : n) - S[r];
-  sel[r] = len >= min_run ? 1u : 0u;
-}
-
-__global__ __launch_bounds__(WG) void k_run_mark(const u32* S, u64 nruns, u64 n, const u32* sel,
-                                                 const u64* ids, u32* bm_at, u32* start,
-                                                 u32* len) {
-  const u64 r = (u64)blockIdx.x * WG + threadIdx.x;
-  if (r >= nruns || !sel[r]) return;
+__global__ __launch_bounds__(WG) void k_run_mark(const u32* rs, const u32* re, u32 nruns,
+                                                 const u32* keep, const u64* ids, u32* bm_at,
+                                                 u32* start, u32* len) {
+  const u32 r = blockIdx.x * WG + threadIdx.x;
+  if (r >= nruns || !keep[r]) return;
   const u64 id = ids[r];
-  bm_at[S[r]] = (u32)id;
-  start[id] = S[r];
-  len[id] = (u32)((r + 1 < nruns ? (u64)S[r + 1] : n) - S[r]);
+  bm_at[rs[r]] = (u32)id;
+  start[id] = rs[r];
+  len[id] = re[r] - rs[r];
 }
 
 // One workgroup per selected run: set the bits of its last-column values.
@@ -1127,53 +1147,51 @@ void build_directory(Ctx c, const u32* col, u64 n, u32 vmax, u32* dir) {
 u32 build_run_bitmaps(Ctx c, u32 k, const u32* const* cols, u64 n, u32 vmax, u32 min_run,
                       u64 max_bytes, DBuf<u32>* bm_at, DBuf<u32>* bm, u32* words) {
   if (k < 2 || k > (u32)MAXA || n < min_run || n >= 0xffffffffull) return 0;
+  if (min_run < 2 * RUN_PROBE) min_run = 2 * RUN_PROBE;
   Prefix p{};
   for (u32 j = 0; j + 1 < k; ++j) p.c[j] = cols[j];
-  DBuf<u32> flags(c.mem, n);
-  DBuf<u64> pos(c.mem, n), tot(c.mem, 1);
-  k_run_flags<<<grid1(n), WG, 0, c.s>>>(p, k - 1, n, flags.get());
+  // At most one run per probe row can be long enough.
+  const u64 probes = n / RUN_PROBE + 1;
+  const u32 cap = (u32)std::min<u64>(probes, 1u << 24);
+  DBuf<u32> cnt(c.mem, 1), rs(c.mem, cap), re(c.mem, cap);
+  fill_u32(c, cnt.get(), 1, 0);
+  k_run_probe<<<grid1(probes), WG, 0, c.s>>>(p, k - 1, n, min_run, cnt.get(), cap, rs.get(),
+                                              re.get());
   WCDL_HIP(hipGetLastError());
-  scan_u32_excl(c, flags.get(), pos.get(), n, tot.get());
-  u64 nruns = 0;
-  WCDL_HIP(hipMemcpyAsync(&nruns, tot.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
+  u32 nr = 0;
+  WCDL_HIP(hipMemcpyAsync(&nr, cnt.get(), sizeof(u32), hipMemcpyDeviceToHost, c.s));
   WCDL_HIP(hipStreamSynchronize(c.s));
-  DBuf<u32> S(c.mem, nruns);
-  k_run_starts<<<grid1(n), WG, 0, c.s>>>(flags.get(), pos.get(), n, S.get());
-  WCDL_HIP(hipGetLastError());
-  DBuf<u32> hist(c.mem, 64);
-  fill_u32(c, hist.get(), 64, 0);
-  k_run_loghist<<<grid1(nruns), WG, 0, c.s>>>(S.get(), nruns, n, hist.get());
-  WCDL_HIP(hipGetLastError());
-  u32 h[64];
-  WCDL_HIP(hipMemcpyAsync(h, hist.get(), sizeof(h), hipMemcpyDeviceToHost, c.s));
+  nr = std::min(nr, cap);
+  if (nr == 0) return 0;
+  // Keep the longest runs that fit the budget: threshold = a run length.
+  std::vector<u32> hs(nr), he(nr);
+  WCDL_HIP(hipMemcpyAsync(hs.data(), rs.get(), nr * sizeof(u32), hipMemcpyDeviceToHost, c.s));
+  WCDL_HIP(hipMemcpyAsync(he.data(), re.get(), nr * sizeof(u32), hipMemcpyDeviceToHost, c.s));
   WCDL_HIP(hipStreamSynchronize(c.s));
+  std::vector<u32> lens(nr);
+  for (u32 r = 0; r < nr; ++r) lens[r] = he[r] - hs[r];
+  std::sort(lens.begin(), lens.end(), std::greater<u32>());
   const u64 w = ((u64)vmax >> 5) + 1;
-  // Raise the threshold (a power of two) until the bitmaps fit.
-  u32 b0 = 0;
-  while ((1u << b0) < min_run) ++b0;
+  if (n * 4 + w * 4 > max_bytes) return 0;
+  const u64 fit = (max_bytes - n * 4) / (w * 4);
+  // All runs if they fit, else those longer than the (fit+1)-th longest.
+  const u32 thr = nr <= fit ? min_run : lens[fit] + 1;
   u64 nsel = 0;
-  for (;; ++b0) {
-    if (b0 >= 32) return 0;
-    nsel = 0;
-    for (u32 b = b0; b < 64; ++b) nsel += h[b];
-    if (nsel == 0) return 0;
-    if (nsel * w * 4 + n * 4 <= max_bytes) break;
-  }
-  const u32 thr = 1u << b0;
-  DBuf<u32> sel(c.mem, nruns);
-  DBuf<u64> ids(c.mem, nruns);
-  k_run_select<<<grid1(nruns), WG, 0, c.s>>>(S.get(), nruns, n, thr, sel.get());
+  for (u32 r = 0; r < nr; ++r) nsel += lens[r] >= thr ? 1 : 0;
+  if (nsel == 0) return 0;
+  DBuf<u32> keep(c.mem, nr);
+  DBuf<u64> ids(c.mem, nr);
+  k_run_keep<<<grid1(nr), WG, 0, c.s>>>(rs.get(), re.get(), nr, thr, keep.get());
   WCDL_HIP(hipGetLastError());
-  scan_u32_excl(c, sel.get(), ids.get(), nruns, nullptr);
+  scan_u32_excl(c, keep.get(), ids.get(), nr, nullptr);
   *bm_at = DBuf<u32>(c.mem, n);
   *bm = DBuf<u32>(c.mem, nsel * w);
   fill_u32(c, bm_at->get(), n, NONE);
   fill_u32(c, bm->get(), nsel * w, 0);
   DBuf<u32> st(c.mem, nsel), ln(c.mem, nsel);
-  k_run_mark<<<grid1(nruns), WG, 0, c.s>>>(S.get(), nruns, n, sel.get(), ids.get(), bm_at->get(),
-                                          st.get(), ln.get());
+  k_run_mark<<<grid1(nr), WG, 0, c.s>>>(rs.get(), re.get(), nr, keep.get(), ids.get(),
+                                        bm_at->get(), st.get(), ln.get());
   WCDL_HIP(hipGetLastError());
-  if (nsel > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "too many run bitmaps");
   k_run_bits<<<(u32)nsel, WG, 0, c.s>>>(cols[k - 1], st.get(), ln.get(), (u32)w, bm->get());
   WCDL_HIP(hipGetLastError());
   WCDL_HIP(hipStreamSynchronize(c.s));
