@@ -34,7 +34,7 @@ namespace wcdl {
 namespace {
 
 constexpr int WG = 256;
-constexpr int LEAF_K = 4;  // leaf candidates per lane and step
+constexpr int LEAF_K = 2;  // leaf candidates per lane and step
 constexpr int XP_RPT = 8;                         // cross-product rows per thread
 constexpr u32 XP_ROWS = (u32)WG * XP_RPT;         // rows per cross-product workgroup
 constexpr u32 XP_KEYS = 1024;                     // root keys cached per workgroup
