@@ -750,8 +750,22 @@ Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
   // latency, so LDS goes to more resident workgroups rather than to longer
   // buffers (measured on the triangle join: 17% faster than 512 items).
   const u32 cap = 256;
-  const u32 words = layout(cap);
+  u32 words = layout(cap);
   if (words * 4 > 150 * 1024) throw Error(WCDL_E_UNSUPPORTED, "join too deep for LDS; split the rule");
+  // A survivor buffer lets every thread write whole rows; it is added only
+  // where it costs no resident workgroup (160 KB of LDS per CU; each
+  // workgroup's share, static state included, counted in whole KB, which is
+  // what the 4-clique plan measures: 32.6 KB per workgroup left 4 resident,
+  // not 5; more than 6 per CU do not fit the registers anyway).
+  P.off_emit = NONE;
+  {
+    auto per_cu = [](u32 bytes) { return (160u * 1024u) / ((bytes + 1024u + 1023u) / 1024u * 1024u); };
+    const u32 extra = EMIT_ROWS + EMIT_ROWS / 4;
+    if (per_cu((words + extra) * 4) >= std::min(per_cu(words * 4), 6u)) {
+      P.off_emit = words;
+      words += extra;
+    }
+  }
   P.cap = cap;
   P.lds_words = words;
   v.lds_bytes = words * 4;

@@ -215,6 +215,8 @@ struct DPlan {
   u32 cap;                // items per level buffer
   u32 off_val[MAXV], off_lo[MAXV], off_hi[MAXV], off_drv[MAXV], off_clo[MAXV],
       off_chi[MAXV], off_pre[MAXV];
+  u32 off_emit;           // survivors of an emitted chunk (EMIT_ROWS values, then
+                          // EMIT_ROWS item bytes), or NONE: lanes write their own
   u32 lds_words;
 };
 
@@ -295,6 +297,8 @@ void join_root_compact(Ctx c, const u32* col, const u32* d_rng0, u32 atom, u32 n
 // per-key (lo, size) of every level >= 1 into klo/kd ([m][K]).
 void join_histogram(Ctx c, const DPlan* d_plan, const RootSpace& rs, u64* W, u32* klo, u32* kd,
                     u32 m);
+// Candidates of one leaf chunk (leaf candidates per lane x workgroup size).
+constexpr u32 EMIT_ROWS = 512;
 constexpr u64 STAGE_CHUNK = 4096;
 // Count (mode 0), materialize (mode 1) or count-and-stage (mode 2) over
 // workgroups wg0 + [0, nwg), or over the listed workgroups if wg_list is set.

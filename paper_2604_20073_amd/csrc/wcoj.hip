@@ -35,6 +35,7 @@ namespace {
 
 constexpr int WG = 256;
 constexpr int LEAF_K = 2;  // leaf candidates per lane and step
+static_assert(LEAF_K * WG == (int)EMIT_ROWS, "the planner sizes the survivor buffer");
 constexpr int XP_RPT = 8;                         // cross-product rows per thread
 constexpr u32 XP_ROWS = (u32)WG * XP_RPT;         // rows per cross-product workgroup
 constexpr u32 XP_KEYS = 1024;                     // root keys cached per workgroup
@@ -454,19 +455,56 @@ __device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, Em
   u64 tot;
   u64 rk = block_excl_scan(mine, st.sh, &tot);
   tot = uni(tot);
-  if (MODE == 1) {
+  // A new arena chunk when this chunk's rows pass the covered range
+  // (tot <= K*WG <= STAGE_CHUNK: at most one per call).
+  const bool take = MODE == 2 && !em.ovf && em.out + tot > em.covered;
+  const u64 seq = em.covered / STAGE_CHUNK;
+  if (take && threadIdx.x == 0) {
+    const u64 c = atomicAdd(reinterpret_cast<unsigned long long*>(P->stage_next), 1ull);
+    if (c < P->stage_chunks) P->chunk_tag[c] = (b << 32) | seq;
+    st.alloc = c;
+  }
+  if (P->off_emit != NONE) {
+    // Survivors in rank order in LDS (value, then parent item: items of a
+    // level buffer are below 256), then every thread writes whole rows: the
+    // row code runs once per row instead of once per candidate slot.
+    u32* cv = B.sm + P->off_emit;
+    uint8_t* ci = reinterpret_cast<uint8_t*>(cv + K * WG);
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (alive[k]) emit_row(P, B, L, i[k], v[k], obase + em.out + rk++);
-  } else {
-    if (!em.ovf && em.out + tot > em.covered) {
-      // tot <= K*WG <= STAGE_CHUNK: at most one new chunk per call.
-      const u64 seq = em.covered / STAGE_CHUNK;
-      if (threadIdx.x == 0) {
-        const u64 c = atomicAdd(reinterpret_cast<unsigned long long*>(P->stage_next), 1ull);
-        if (c < P->stage_chunks) P->chunk_tag[c] = (b << 32) | seq;
-        st.alloc = c;
+    for (int k = 0; k < K; ++k) {
+      if (alive[k]) {
+        cv[rk] = v[k];
+        ci[rk] = (uint8_t)i[k];
+        ++rk;
       }
+    }
+    __syncthreads();
+    if (take) {
+      const u64 c = uni(st.alloc);
+      if (c >= P->stage_chunks) {
+        em.ovf = 1;
+      } else {
+        if (seq & 1) em.chunk1 = c; else em.chunk0 = c;
+        em.covered += STAGE_CHUNK;
+      }
+    }
+    if (MODE == 1 || !em.ovf) {
+      for (u32 r = threadIdx.x; r < (u32)tot; r += WG) {
+        const u32 ii = ci[r], vv = cv[r];
+        const u64 row = em.out + r;
+        if (MODE == 1) {
+          emit_row(P, B, L, ii, vv, obase + row);
+        } else {
+          const u64 c = ((row / STAGE_CHUNK) & 1) ? em.chunk1 : em.chunk0;
+          stage_row(P, B, L, ii, vv, c * STAGE_CHUNK + (row % STAGE_CHUNK));
+        }
+      }
+    }
+    // cv / ci are next written after the next call's rank scan, which every
+    // thread reaches only after finishing these rows.
+  } else {
+    // Each lane writes its own survivors.
+    if (take) {
       __syncthreads();
       const u64 c = uni(st.alloc);
       if (c >= P->stage_chunks) {
@@ -476,13 +514,17 @@ __device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, Em
         em.covered += STAGE_CHUNK;
       }
     }
-    if (!em.ovf) {
+    if (MODE == 1 || !em.ovf) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (alive[k]) {
-          const u64 r = em.out + rk++;
-          const u64 c = ((r / STAGE_CHUNK) & 1) ? em.chunk1 : em.chunk0;
-          stage_row(P, B, L, i[k], v[k], c * STAGE_CHUNK + (r % STAGE_CHUNK));
+          const u64 row = em.out + rk++;
+          if (MODE == 1) {
+            emit_row(P, B, L, i[k], v[k], obase + row);
+          } else {
+            const u64 c = ((row / STAGE_CHUNK) & 1) ? em.chunk1 : em.chunk0;
+            stage_row(P, B, L, i[k], v[k], c * STAGE_CHUNK + (row % STAGE_CHUNK));
+          }
         }
       }
     }
