@@ -76,6 +76,9 @@ typedef int32_t wcdl_status;
                                     full relation instead of into a small head
                                     run that is flushed into the body past a
                                     size ratio (Sec. 4, Merge) */
+#define WCDL_F_RUN_BITMAPS_OFF 0x40u /* never build run bitmaps: leaf probes always
+                                    search (bitmaps answer probes into runs of
+                                    >= 512 rows of copies a batch does not write) */
 #define WCDL_F_BATCHED 0x10u     /* batched mode: the engine holds many independent
                                     instances of one program.  Every relation gets
                                     an implicit leading column, the instance id:

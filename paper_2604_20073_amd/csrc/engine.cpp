@@ -1052,7 +1052,8 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
         DSource& src = P.lvl[L].src[s2];
         src.bm_at = src.bm = nullptr;
         src.bm_words = src.bm_min = 0;
-        if (L + 1 == P.m && L > 0 && src.alias == NONE && !v.want_dir[L][s2] && !e->serving) {
+        if (L + 1 == P.m && L > 0 && src.alias == NONE && !v.want_dir[L][s2] && !e->serving &&
+            !(e->cfg.flags & WCDL_F_RUN_BITMAPS_OFF)) {
           // Leaf sources of copies that no version of this batch writes.
           const AtomUse& u = v.atoms[src.atom];
           bool stable = !u.delta;

@@ -10,8 +10,9 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2604_20073_amd import (WCDL_F_BALANCE_OFF, WCDL_F_HEAD_BODY_OFF, WCDL_F_STAGE_OFF,
-                                  WCDL_F_STREAMS_OFF, WCDL_F_XPROD_OFF, Engine, WcdlError)
+from paper_2604_20073_amd import (WCDL_F_BALANCE_OFF, WCDL_F_HEAD_BODY_OFF, WCDL_F_RUN_BITMAPS_OFF,
+                                  WCDL_F_STAGE_OFF, WCDL_F_STREAMS_OFF, WCDL_F_XPROD_OFF, Engine,
+                                  WcdlError)
 from paper_2604_20073_amd import workloads as W
 from tests.checkers import render
 from tests.test_oracle_pins import ANDERSEN, ARITY, C4, PROGRAMS, Q4, TC, TRI
@@ -120,7 +121,7 @@ def test_andersen_small():
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("flags", [WCDL_F_BALANCE_OFF, WCDL_F_STREAMS_OFF, WCDL_F_XPROD_OFF,
-                                   WCDL_F_STAGE_OFF, WCDL_F_HEAD_BODY_OFF,
+                                   WCDL_F_STAGE_OFF, WCDL_F_HEAD_BODY_OFF, WCDL_F_RUN_BITMAPS_OFF,
                                    WCDL_F_BALANCE_OFF | WCDL_F_STREAMS_OFF | WCDL_F_XPROD_OFF])
 def test_flags_do_not_change_results(flags):
     edges = W.rmat_graph(10, 6000, 31)
@@ -511,3 +512,34 @@ def test_merge_path_six_columns_many_tiles():
              "w(a2,b,c,d,e,f) :- w(a,b,c,d,e,f), nxt(a,a2), a < 60.")
     got, stats = check_parity({"s": 6, "nxt": 2, "w": 6}, rules, {"s": seed, "nxt": nxt})
     assert len(got["w"]) > 50000 and stats["rounds"] > 10
+
+
+@pytest.mark.parametrize("flags", [0, WCDL_F_RUN_BITMAPS_OFF])
+def test_hub_runs_bitmaps(flags):
+    """Hubs with thousands of neighbours: leaf probes into their adjacency
+    runs (>= 512 rows) are answered by run bitmaps, or searched with the
+    bitmaps off; triangles and 4-cliques through the hubs equal the oracle's.
+    A second run reuses the staged count pass."""
+    rng = np.random.default_rng(123)
+    n = 6000
+    hubs = np.arange(8, dtype=np.uint32)
+    rows = [np.stack([np.full(3000, h, np.uint32), rng.choice(np.arange(8, n, dtype=np.uint32), 3000,
+                                                                  replace=False)], axis=1) for h in hubs]
+    rows.append(np.stack([np.repeat(hubs, 8), np.tile(hubs, 8)], axis=1))  # hubs among themselves
+    rows.append(rng.integers(8, n, size=(40000, 2)).astype(np.uint32))
+    edges = np.unique(np.concatenate(rows), axis=0)
+    rels = {"edge": 2, "tri": 3, "q": 4}
+    rules = TRI + "\n" + Q4
+    _, expect = oracle.evaluate(rels, rules, {"edge": edges})
+    e = Engine(flags=flags)
+    for nm, k in rels.items():
+        e.declare(nm, k)
+    e.add_rules(rules)
+    for _ in range(2):
+        e.clear("edge")
+        e.load("edge", edges)
+        e.run()
+        assert np.array_equal(e.read_numpy("tri"), expect["tri"])
+        assert np.array_equal(e.read_numpy("q"), expect["q"])
+    assert len(expect["q"]) > 0
+    e.close()
