@@ -79,6 +79,11 @@ typedef int32_t wcdl_status;
 #define WCDL_F_RUN_BITMAPS_OFF 0x40u /* never build run bitmaps: leaf probes always
                                     search (bitmaps answer probes into runs of
                                     >= 512 rows of copies a batch does not write) */
+#define WCDL_F_GROUPED_SORT_OFF 0x80u /* sort every head chunk with the radix sort,
+                                    also where the join already emits it in order
+                                    of all but its last column (Sec. 4, Compute
+                                    Delta: the grouped sort orders and dedups
+                                    such chunks one LDS tile of groups at a time) */
 #define WCDL_F_BATCHED 0x10u     /* batched mode: the engine holds many independent
                                     instances of one program.  Every relation gets
                                     an implicit leading column, the instance id:

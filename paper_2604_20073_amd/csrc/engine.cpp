@@ -406,6 +406,9 @@ struct Version {
   std::vector<std::vector<bool>> want_dir;  // per level, per source: unnarrowed first column
   DPlan plan{};                 // pointers filled at evaluation time
   bool sorted_output = false;   // rows come out sorted by head columns, unique
+  // Leading head columns that are the first join levels in order: the rows
+  // come out non-decreasing in them (with repeats if levels follow them).
+  u32 sorted_prefix = 0;
   u32 lds_bytes = 0;
 };
 
@@ -513,11 +516,33 @@ std::vector<u32> choose_order(const Rule& r, int delta_atom) {
   } else {
     cand = vars;
   }
-  u32 root = cand[0];
-  for (u32 v : cand)
-    if (better(v, root, false)) root = v;
-  order.push_back(root);
-  bound[root] = true;
+  // Delta-first with the head's leading variables: when the delta atom's
+  // leading columns are the head's leading variables (all but at most its
+  // last), taking them first reads the delta in its stored order and emits
+  // rows grouped by all but the last head column, which the grouped sort
+  // orders without the radix passes.
+  if (delta_atom >= 0 && r.head.t.size() >= 2) {
+    const auto& dt = r.body[delta_atom].t;
+    std::vector<u32> pre;
+    for (size_t j = 0; j < dt.size() && j < r.head.t.size(); ++j) {
+      if (!dt[j].var || !r.head.t[j].var || dt[j].v != r.head.t[j].v) break;
+      if (std::find(pre.begin(), pre.end(), dt[j].v) != pre.end()) break;
+      pre.push_back(dt[j].v);
+    }
+    if (pre.size() + 1 >= r.head.t.size()) {
+      for (u32 v : pre) {
+        order.push_back(v);
+        bound[v] = true;
+      }
+    }
+  }
+  if (order.empty()) {
+    u32 root = cand[0];
+    for (u32 v : cand)
+      if (better(v, root, false)) root = v;
+    order.push_back(root);
+    bound[root] = true;
+  }
   while (order.size() < vars.size()) {
     int best = -1;
     bool any_conn = false;
@@ -712,11 +737,14 @@ Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
   // Head.
   P.head_arity = (u32)r.head.t.size();
   bool sorted = (P.head_arity == m);
+  u32 prefix = 0;
   for (u32 h = 0; h < P.head_arity; ++h) {
     P.head[h] = operand(r.head.t[h]);
     if (!(P.head[h].is_var && P.head[h].v == h)) sorted = false;
+    if (prefix == h && P.head[h].is_var && P.head[h].v == h) ++prefix;
   }
   v.sorted_output = sorted;
+  v.sorted_prefix = prefix;
   // Fast paths.
   if (m >= 2) {
     const DLevel& leaf = P.lvl[m - 1];
@@ -1006,8 +1034,10 @@ void repartition(Engine* e, VRun& R, u64 max_rows, Stats& st) {
 
 // Raw head rows of one chunk (canonical column order, unsorted unless
 // `presorted`: sorted, unique, above every row of the head's earlier chunks,
-// and from the head's only version).
-using Sink = std::function<void(u32 rel, Cols&& rows, bool presorted)>;
+// and from the head's only version).  `grouped`: the rows, all from one
+// version, are non-decreasing in their first `grouped` columns (repeats are
+// possible unless `presorted`).
+using Sink = std::function<void(u32 rel, Cols&& rows, bool presorted, u32 grouped)>;
 
 // Evaluate a set of rule versions over the current relations and hand every
 // chunk of raw head rows to `sink`.
@@ -1361,11 +1391,20 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
   for (auto& R : runs)
     if (!R.skip && !chunked.count(R.v->head_rel)) check_flag(R);
   st.phase[WCDL_PH_MATERIALIZE] += ms_since(t_mat);
+  // Rows of one version keep its emission order (Sec. 3.3: each slice's rows
+  // at its scanned offset), so a version's sorted prefix holds for its head.
+  auto grouped_of = [&](u32 rel) -> u32 {
+    if (nver[rel] != 1 || e->serving) return 0;
+    for (auto& R : runs)
+      if (!R.skip && R.v->head_rel == rel) return R.v->sorted_prefix;
+    return 0;
+  };
   for (auto& kv : whole) {
     bool sorted = nver[kv.first] == 1;
     for (auto& R : runs)
       if (!R.skip && R.v->head_rel == kv.first) sorted = sorted && R.v->sorted_output;
-    sink(kv.first, std::move(kv.second), sorted);
+    const u32 g = grouped_of(kv.first);
+    sink(kv.first, std::move(kv.second), sorted, g);
   }
   whole.clear();
   // ---- Chunked heads: one version and one range at a time.
@@ -1418,7 +1457,7 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
       st.candidates += chunk.n;
       st.phase[WCDL_PH_MATERIALIZE] += ms_since(t_chunk);
       // Ranges go in workgroup order, so a sorted head's chunks ascend.
-      sink(R.v->head_rel, std::move(chunk), in_order[R.v->head_rel]);
+      sink(R.v->head_rel, std::move(chunk), in_order[R.v->head_rel], grouped_of(R.v->head_rel));
       recycle(e);
     }
     // The staging arena of this version is no longer needed.
@@ -1447,9 +1486,57 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
   }
 }
 
+// Sorted, deduplicated rows of a chunk whose first `grouped` columns are
+// already non-decreasing: only repeats to drop when that is every column; a
+// bitmap per group in LDS when it is all but the last and the last column's
+// values are small against the rows per group; else the radix sort.
+Cols sort_unique(Engine* e, Cols rows, u32 grouped) {
+  const u32 k = (u32)rows.col.size();
+  if (rows.n == 0 || (e->cfg.flags & WCDL_F_GROUPED_SORT_OFF)) grouped = 0;
+  if (grouped >= k && k > 0) {
+    // Sorted already; repeats remain where the join has levels past the head.
+    Ctx c = ctx(e);
+    Cols out;
+    out.order = rows.order;
+    std::vector<u32*> op;
+    for (u32 j = 0; j < k; ++j) {
+      out.col.emplace_back(c.mem, rows.n);
+      op.push_back(out.col.back().get());
+    }
+    std::vector<const u32*> in(rows.ptrs());
+    out.n = unique_rows(c, k, in.data(), rows.n, op.data());
+    return out;
+  }
+  if (k >= 2 && grouped + 1 == k) {
+    Ctx c = ctx(e);
+    DBuf<u32> d_or(c.mem, 1);
+    const u32* last = rows.col[k - 1].get();
+    column_or(c, 1, &last, rows.n, d_or.get());
+    u32 h_or = 0;
+    WCDL_HIP(hipMemcpyAsync(&h_or, d_or.get(), sizeof(u32), hipMemcpyDeviceToHost, c.s));
+    WCDL_HIP(hipStreamSynchronize(c.s));
+    const u32 zbits = bits_of(h_or);
+    if (zbits <= 18) {
+      std::vector<const u32*> in(rows.ptrs());
+      Cols out;
+      out.order = rows.order;
+      std::vector<u32*> op;
+      for (u32 j = 0; j < k; ++j) {
+        out.col.emplace_back(c.mem, rows.n);
+        op.push_back(out.col.back().get());
+      }
+      if (sort_unique_grouped(c, k, in.data(), rows.n, zbits, op.data(), &out.n)) return out;
+    }
+  }
+  Cols srt = sort_rows(e, 0, rows.order, std::vector<const u32*>(rows.ptrs()), rows.n, true);
+  rows = Cols();
+  return srt;
+}
+
 // Fold one chunk of raw rows of relation `rel` into `acc`, the rows new this
 // round: acc += unique(rows) \ full \ acc (Compute Delta, Sec. 4).
-void absorb_chunk(Engine* e, u32 rel, Cols&& rows, bool presorted, Cols& acc, Stats& st) {
+void absorb_chunk(Engine* e, u32 rel, Cols&& rows, bool presorted, u32 grouped, Cols& acc,
+                  Stats& st) {
   Relation& R = e->rels[rel];
   auto t = Clock::now();
   if (presorted && R.full.n == 0 && R.head.n == 0) {
@@ -1457,8 +1544,7 @@ void absorb_chunk(Engine* e, u32 rel, Cols&& rows, bool presorted, Cols& acc, St
     if (acc.n == 0) acc = std::move(rows);
     else if (rows.n) acc = merged(e, 0, acc, rows);
   } else {
-    Cols srt = sort_rows(e, 0, rows.order, std::vector<const u32*>(rows.ptrs()), rows.n, true);
-    rows = Cols();
+    Cols srt = sort_unique(e, std::move(rows), grouped);
     recycle(e);
     Cols d = difference(e, 0, srt, R.full, &R.head);
     srt = Cols();
@@ -1532,11 +1618,11 @@ void commit_delta(Engine* e, u32 rel, Cols& d, Stats& st, bool consume = false,
 // Evaluate versions and return the rows new to each head relation.
 std::map<u32, Cols> new_rows(Engine* e, std::vector<Version>& vs, Stats& st) {
   std::map<u32, Cols> acc;
-  eval_batch(e, vs, st, [&](u32 rel, Cols&& rows, bool presorted) {
+  eval_batch(e, vs, st, [&](u32 rel, Cols&& rows, bool presorted, u32 grouped) {
     auto it = acc.find(rel);
     if (it == acc.end())
       it = acc.emplace(rel, empty_cols(e->rels[rel].arity, canonical(e->rels[rel].arity))).first;
-    absorb_chunk(e, rel, std::move(rows), presorted, it->second, st);
+    absorb_chunk(e, rel, std::move(rows), presorted, grouped, it->second, st);
   });
   return acc;
 }

@@ -5,6 +5,8 @@
 // radix sort for Build Index and a single-pass merge for Merge (Sec. 4);
 // these are this engine's own versions of both.
 
+#include <algorithm>
+
 #include "wcdl_internal.h"
 
 namespace wcdl {
@@ -281,6 +283,102 @@ __global__ __launch_bounds__(WG) void k_rs_scatter(ColsIn in, ColsOut out, u32 k
       dst[gofs[d] + (t - dstart[d])] = tile[t];
     }
     __syncthreads();
+  }
+}
+
+// ---- grouped sort -----------------------------------------------------------
+//
+// Rows already non-decreasing in columns 0..k-2 (groups) and unsorted, with
+// repeats, in column k-1 -- what a join emits when the head starts with the
+// join's first variables -- whose last values are small (below 2^zbits):
+// each group gets a bitmap of its last values in LDS, one bit set per row,
+// and the set bits read back in order are the group's sorted unique rows.
+// Two streaming passes over the last column (count, then write) replace the
+// global radix passes over every column.
+
+constexpr u32 GB_WORDS = 8192;   // bitmap words of one tile (32 KB of LDS)
+constexpr u32 GB_GROUPS = 1024;  // most groups in one tile
+
+// flags[i] = 1 where row i starts a group (differs from row i-1 in 0..kp-1).
+__global__ __launch_bounds__(WG) void k_group_flags(ColsIn a, u32 kp, u64 n, u32* flags) {
+  const u64 i = (u64)blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  u32 f = i == 0 ? 1u : 0u;
+  for (u32 j = 0; j < kp && !f; ++j) f = a.c[j][i] != a.c[j][i - 1] ? 1u : 0u;
+  flags[i] = f;
+}
+
+__global__ __launch_bounds__(WG) void k_group_starts(const u32* flags, const u64* pos, u64 n,
+                                                     u64* gs) {
+  const u64 i = (u64)blockIdx.x * WG + threadIdx.x;
+  if (i < n && flags[i]) gs[pos[i]] = i;
+}
+
+// Tile t = groups [t*G, (t+1)*G), `wpg` bitmap words each.  EMIT = false:
+// cnt[t] = the tile's unique rows.  EMIT = true: those rows, in order, from
+// off[t] on -- leading columns from the group's first row, last column from
+// the bit.  Dynamic LDS: G*wpg bitmap words, then G+1 group starts.
+template <bool EMIT>
+__global__ __launch_bounds__(WG) void k_group_bitmap(ColsIn a, u32 k, u64 n, const u64* gs,
+                                                     u64 ng, u32 G, u32 wpg, u32* cnt,
+                                                     const u64* off, ColsOut o) {
+  extern __shared__ u32 lds[];
+  __shared__ u64 sh[WG / 64];
+  u32* bm = lds;
+  u64* gsl = reinterpret_cast<u64*>(lds + ((G * wpg + 1u) & ~1u));
+  const u64 g0 = (u64)blockIdx.x * G;
+  const u32 ngl = (u32)((ng - g0) < G ? (ng - g0) : G);
+  const u32 W = ngl * wpg;
+  for (u32 w = threadIdx.x; w < W; w += WG) bm[w] = 0;
+  for (u32 j = threadIdx.x; j <= ngl; j += WG) gsl[j] = g0 + j < ng ? gs[g0 + j] : n;
+  __syncthreads();
+  const u32* last = a.c[k - 1];
+  const u64 r0 = gsl[0], r1 = gsl[ngl];
+  for (u64 r = r0 + threadIdx.x; r < r1; r += WG) {
+    u32 lo = 0, hi = ngl;  // gsl[lo] <= r < gsl[hi]
+    while (hi - lo > 1) {
+      const u32 mid = (lo + hi) >> 1;
+      if (gsl[mid] <= r) lo = mid; else hi = mid;
+    }
+    const u32 z = last[r];
+    atomicOr(&bm[lo * wpg + (z >> 5)], 1u << (z & 31));
+  }
+  __syncthreads();
+  if (!EMIT) {
+    u64 mine = 0;
+    for (u32 w = threadIdx.x; w < W; w += WG) mine += (u64)__popc(bm[w]);
+    u64 tot;
+    block_excl_scan(mine, sh, &tot);
+    if (threadIdx.x == 0) cnt[blockIdx.x] = (u32)tot;
+    return;
+  }
+  // Rounds of WG consecutive words: one word per thread, positions by a
+  // block scan, so a round's rows are written contiguously.
+  u64 base = off[blockIdx.x];
+  for (u32 w0 = 0; w0 < W; w0 += WG) {
+    const u32 w = w0 + threadIdx.x;
+    u32 bits = w < W ? bm[w] : 0u;
+    u64 tot;
+    u64 at = base + block_excl_scan((u64)__popc(bits), sh, &tot);
+    if (bits) {
+      const u32 g = w / wpg;
+      const u32 zhi = (w - g * wpg) << 5;
+      const u64 row = gsl[g];
+      u32 pre[MAXA];
+#pragma unroll
+      for (u32 j = 0; j < (u32)MAXA; ++j)
+        if (j + 1 < k) pre[j] = a.c[j][row];
+      while (bits) {
+        const u32 bit = (u32)__ffs(bits) - 1u;
+        bits &= bits - 1u;
+#pragma unroll
+        for (u32 j = 0; j < (u32)MAXA; ++j)
+          if (j + 1 < k) o.c[j][at] = pre[j];
+        o.c[k - 1][at] = zhi | bit;
+        ++at;
+      }
+    }
+    base += tot;
   }
 }
 
@@ -580,6 +678,48 @@ void radix_sort_rows(Ctx c, u32 k, const u32* const* in_cols, u32* const* out_co
     for (u32 j = 0; j < k; ++j) src_v[j] = dst_v[j];
     src = src_v.data();
   }
+}
+
+bool sort_unique_grouped(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32 zbits,
+                         u32* const* out_cols, u64* out_n) {
+  if (k < 2 || k > (u32)MAXA || zbits > 18) return false;
+  *out_n = 0;
+  if (n == 0) return true;
+  const ColsIn A = cols_in(k, in_cols);
+  DBuf<u32> flags(c.mem, n);
+  DBuf<u64> pos(c.mem, n), tot(c.mem, 1);
+  k_group_flags<<<grid_for(n, WG), WG, 0, c.s>>>(A, k - 1, n, flags.get());
+  WCDL_HIP(hipGetLastError());
+  scan_u32_excl(c, flags.get(), pos.get(), n, tot.get());
+  u64 ng = 0;
+  WCDL_HIP(hipMemcpyAsync(&ng, tot.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
+  WCDL_HIP(hipStreamSynchronize(c.s));
+  const u32 wpg = zbits <= 5 ? 1u : 1u << (zbits - 5);
+  // Each pass scans every group's bitmap: worth it while that is at most
+  // two words per row.
+  if (ng * wpg > 2 * n) return false;
+  DBuf<u64> gs(c.mem, ng);
+  k_group_starts<<<grid_for(n, WG), WG, 0, c.s>>>(flags.get(), pos.get(), n, gs.get());
+  WCDL_HIP(hipGetLastError());
+  flags = DBuf<u32>();
+  pos = DBuf<u64>();
+  const u32 G = std::min<u32>(GB_GROUPS, GB_WORDS / wpg);
+  const u64 ntiles = ceil_div(ng, (u64)G);
+  if (ntiles > 0x7fffffffull) return false;
+  const size_t lds = (size_t)((G * wpg + 1u) & ~1u) * 4 + (size_t)(G + 1) * 8;
+  DBuf<u32> cnt(c.mem, ntiles);
+  DBuf<u64> off(c.mem, ntiles), total(c.mem, 1);
+  const ColsOut O = cols_out(k, out_cols);
+  k_group_bitmap<false><<<(u32)ntiles, WG, lds, c.s>>>(A, k, n, gs.get(), ng, G, wpg, cnt.get(),
+                                                      nullptr, O);
+  WCDL_HIP(hipGetLastError());
+  scan_u32_excl(c, cnt.get(), off.get(), ntiles, total.get());
+  k_group_bitmap<true><<<(u32)ntiles, WG, lds, c.s>>>(A, k, n, gs.get(), ng, G, wpg, cnt.get(),
+                                                     off.get(), O);
+  WCDL_HIP(hipGetLastError());
+  WCDL_HIP(hipMemcpyAsync(out_n, total.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
+  WCDL_HIP(hipStreamSynchronize(c.s));
+  return true;
 }
 
 u64 unique_rows(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32* const* out_cols) {

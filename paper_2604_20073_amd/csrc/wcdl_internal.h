@@ -264,6 +264,14 @@ void radix_sort_rows(Ctx c, u32 k, const u32* const* in_cols, u32* const* out_co
 // OR of all values of each column (device results in d_or[k]).
 void column_or(Ctx c, u32 k, const u32* const* cols, u64 n, u32* d_or);
 
+// Rows non-decreasing in columns 0..k-2 and unsorted, with repeats, in
+// column k-1 (values below 2^zbits): sorted and deduplicated through one LDS
+// bitmap per group of equal leading columns.  Returns false, having written
+// nothing, where the bitmaps would cost more than the rows (zbits > 18, or
+// more than two bitmap words per row); else *out_n = rows written
+// (synchronises).
+bool sort_unique_grouped(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32 zbits,
+                         u32* const* out_cols, u64* out_n);
 // Unique adjacent rows of a sorted input; returns the count (synchronises).
 u64 unique_rows(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32* const* out_cols);
 // Rows of sorted-unique A absent from sorted-unique B and from the optional

@@ -31,6 +31,7 @@ WCDL_F_STAGE_OFF = 0x8
 WCDL_F_BATCHED = 0x10
 WCDL_F_HEAD_BODY_OFF = 0x20
 WCDL_F_RUN_BITMAPS_OFF = 0x40
+WCDL_F_GROUPED_SORT_OFF = 0x80
 PHASES = ["histogram", "count", "materialize", "delta", "index", "merge", "load", "other"]
 KERNELS = ["join_count", "join_materialize", "join_histogram", "unused"]
 ERRORS = {-1: "E_INVALID", -2: "E_ARITY", -3: "E_UNKNOWN_REL", -4: "E_UNSAFE_RULE",

@@ -10,7 +10,8 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2604_20073_amd import (WCDL_F_BALANCE_OFF, WCDL_F_HEAD_BODY_OFF, WCDL_F_RUN_BITMAPS_OFF,
+from paper_2604_20073_amd import (WCDL_F_BALANCE_OFF, WCDL_F_GROUPED_SORT_OFF, WCDL_F_HEAD_BODY_OFF,
+                                  WCDL_F_RUN_BITMAPS_OFF,
                                   WCDL_F_STAGE_OFF, WCDL_F_STREAMS_OFF, WCDL_F_XPROD_OFF, Engine,
                                   WcdlError)
 from paper_2604_20073_amd import workloads as W
@@ -122,6 +123,7 @@ def test_andersen_small():
 
 @pytest.mark.parametrize("flags", [WCDL_F_BALANCE_OFF, WCDL_F_STREAMS_OFF, WCDL_F_XPROD_OFF,
                                    WCDL_F_STAGE_OFF, WCDL_F_HEAD_BODY_OFF, WCDL_F_RUN_BITMAPS_OFF,
+                                   WCDL_F_GROUPED_SORT_OFF,
                                    WCDL_F_BALANCE_OFF | WCDL_F_STREAMS_OFF | WCDL_F_XPROD_OFF])
 def test_flags_do_not_change_results(flags):
     edges = W.rmat_graph(10, 6000, 31)
@@ -543,3 +545,24 @@ def test_hub_runs_bitmaps(flags):
         assert np.array_equal(e.read_numpy("q"), expect["q"])
     assert len(expect["q"]) > 0
     e.close()
+
+
+@pytest.mark.parametrize("shift,small", [(0, True), ((1 << 18) - 4197, False), (1 << 22, True)])
+@pytest.mark.parametrize("flags", [0, WCDL_F_GROUPED_SORT_OFF])
+def test_grouped_sort_hub_and_small_groups(shift, small, flags):
+    """Transitive closure, whose recursive join emits rows grouped by x: one
+    hub x reaching 120,000 rows with repeats, with or without ~1,600 small
+    groups; node ids shifted so the last column needs 12 bits (bitmaps of
+    128 words, many groups per tile), 18 (one group per tile) or 23 (radix
+    sort).  Equal to the oracle either way."""
+    rng = np.random.default_rng(77)
+    hub = [np.stack([np.zeros(40, np.uint32), np.arange(1, 41, dtype=np.uint32)], axis=1)]
+    for y in range(1, 41):
+        z = rng.choice(np.arange(100, 4196, dtype=np.uint32), 3000, replace=False)
+        hub.append(np.stack([np.full(3000, y, np.uint32), z], axis=1))
+    if small:
+        hub.append(rng.integers(100, 4196, size=(1500, 2)).astype(np.uint32))
+    edges = np.unique(np.concatenate(hub), axis=0).astype(np.uint64)
+    edges = np.where(edges >= 1, edges + shift, edges).astype(np.uint32)
+    got, _ = check_parity({"edge": 2, "path": 2}, TC, {"edge": edges}, flags=flags)
+    assert (got["path"][:, 0] == 0).sum() > 3000
