@@ -19,6 +19,7 @@ constexpr int RS_IPT = 16;     // keys per thread in radix passes
 constexpr int RS_TILE = WG * RS_IPT;  // 4096 keys per tile
 constexpr int SEARCH_IPT = 4;  // rows per thread in tiled searches
 constexpr int SEARCH_TILE = WG * SEARCH_IPT;
+constexpr u32 AF_WORDS = 8192;  // LDS words of splitters in set differences (32 KB)
 
 struct ColsIn { const u32* c[MAXA]; };
 struct ColsOut { u32* c[MAXA]; };
@@ -417,16 +418,21 @@ __device__ inline u64 row_lower_bound(const ColsIn& b, u32 k, u64 lo, u64 hi,
   return lo;
 }
 
-// Range of b that can hold the rows of a's tile [t0, t1): [lb(a[t0]), lb(a[t1-1]) + 1).
-__device__ inline void tile_window(const ColsIn& a, const ColsIn& b, u32 k, u64 t0, u64 t1,
-                                   u64 nb, u64* wlo, u64* whi) {
+// bounds[t] = lower bound in b of a's row t*SEARCH_TILE (t < ntiles),
+// bounds[ntiles] = nb: the rows of a's tile t can only equal rows of b in
+// [bounds[t], bounds[t+1]).  One thread per boundary, so the searches'
+// dependent loads overlap across the whole grid.
+__global__ __launch_bounds__(WG) void k_tile_bounds(ColsIn a, ColsIn b, u32 k, u64 na, u64 nb,
+                                                    u64 ntiles, u64* bounds) {
+  const u64 t = (u64)blockIdx.x * WG + threadIdx.x;
+  if (t > ntiles) return;
+  if (t == ntiles || nb == 0) {
+    bounds[t] = t == ntiles ? nb : 0;
+    return;
+  }
   u32 key[MAXA];
-  load_row(a, k, t0, key);
-  u64 lo = row_lower_bound(b, k, 0, nb, key);
-  load_row(a, k, t1 - 1, key);
-  u64 hi = row_lower_bound(b, k, lo, nb, key);
-  *wlo = lo;
-  *whi = hi < nb ? hi + 1 : nb;
+  load_row(a, k, t * SEARCH_TILE, key);
+  bounds[t] = row_lower_bound(b, k, 0, nb, key);
 }
 
 __global__ __launch_bounds__(WG) void k_adjacent_flags(ColsIn a, u32 k, u64 n, u32* flags) {
@@ -449,28 +455,76 @@ __global__ __launch_bounds__(WG) void k_compact(ColsIn a, ColsOut o, u32 k, u64 
   for (u32 j = 0; j < k; ++j) o.c[j][p] = a.c[j][i];
 }
 
-// flags[i] = 1 if row i of `a` is in neither b nor c (c may be empty).
+// Splitters of a window [lo, hi) of b in LDS: row lo + j*stride for j < ns,
+// column-major (sp[col * S + j]); stride 1 stages the window whole.
+struct Splitters {
+  u64 lo, hi, stride;
+  u32 ns;
+};
+
+__device__ inline void stage_splitters(const ColsIn& b, u32 k, u64 lo, u64 hi, u32 S, u32* sp,
+                                       Splitters* out) {
+  const u64 w = hi - lo;
+  const u64 stride = w <= S ? 1 : (w + S - 1) / S;
+  const u32 ns = (u32)((w + stride - 1) / stride);
+  for (u32 j = threadIdx.x; j < ns; j += WG)
+    for (u32 col = 0; col < k; ++col) sp[col * S + j] = b.c[col][lo + (u64)j * stride];
+  if (threadIdx.x == 0) *out = Splitters{lo, hi, stride, ns};
+}
+
+// Is `key` a row of b?  Lower bound among the splitters in LDS, then among
+// the at most stride-1 rows of b between two splitters.
+__device__ inline bool in_window(const ColsIn& b, u32 k, const Splitters& w, const u32* sp, u32 S,
+                                 const u32 (&key)[MAXA]) {
+  u32 lo = 0, hi = w.ns;  // first splitter >= key
+  while (lo < hi) {
+    const u32 mid = (lo + hi) >> 1;
+    bool less = false;
+#pragma unroll
+    for (int c = 0; c < MAXA; ++c) {
+      if (c < (int)k) {
+        const u32 v = sp[c * S + mid];
+        if (v != key[c]) { less = v < key[c]; break; }
+      }
+    }
+    if (less) lo = mid + 1; else hi = mid;
+  }
+  if (w.stride == 1) {
+    if (lo >= w.ns) return false;
+#pragma unroll
+    for (int c = 0; c < MAXA; ++c)
+      if (c < (int)k && sp[c * S + lo] != key[c]) return false;
+    return true;
+  }
+  const u64 L = lo == 0 ? w.lo : w.lo + (u64)(lo - 1) * w.stride + 1;
+  const u64 R = lo < w.ns ? w.lo + (u64)lo * w.stride : w.hi;
+  const u64 p = row_lower_bound(b, k, L, R, key);
+  return p < w.hi && row_equal(b, k, p, key);
+}
+
+// flags[i] = 1 if row i of `a` is in neither b nor c (c may be empty).  Each
+// tile of a searches the windows of b and c its rows can fall in, through S
+// splitters per window staged in LDS (2*S*k words of dynamic LDS).
 __global__ __launch_bounds__(WG) void k_absent_flags(ColsIn a, ColsIn b, ColsIn c, u32 k, u64 na,
-                                                     u64 nb, u64 nc, u32* flags) {
-  __shared__ u64 win[4];
+                                                     const u64* bb, const u64* bc, u32 S,
+                                                     u32* flags) {
+  extern __shared__ u32 sp[];
+  __shared__ Splitters sw[2];
   const u64 t0 = (u64)blockIdx.x * SEARCH_TILE;
   const u64 t1 = (t0 + SEARCH_TILE < na) ? t0 + SEARCH_TILE : na;
-  if (threadIdx.x == 0) {
-    if (nb) tile_window(a, b, k, t0, t1, nb, &win[0], &win[1]);
-    else win[0] = win[1] = 0;
-  } else if (threadIdx.x == 64) {
-    if (nc) tile_window(a, c, k, t0, t1, nc, &win[2], &win[3]);
-    else win[2] = win[3] = 0;
-  }
+  const u64 blo = bb[blockIdx.x], bhi = bb[blockIdx.x + 1];
+  const u64 clo = bc[blockIdx.x], chi = bc[blockIdx.x + 1];
+  u32* spb = sp;
+  u32* spc = sp + (size_t)S * k;
+  stage_splitters(b, k, blo, bhi, S, spb, &sw[0]);
+  stage_splitters(c, k, clo, chi, S, spc, &sw[1]);
   __syncthreads();
-  const u64 blo = win[0], bhi = win[1], clo = win[2], chi = win[3];
+  const Splitters wb = sw[0], wc = sw[1];
   for (u64 i = t0 + threadIdx.x; i < t1; i += WG) {
     u32 key[MAXA];
     load_row(a, k, i, key);
-    const u64 p = row_lower_bound(b, k, blo, bhi, key);
-    const u64 q = row_lower_bound(c, k, clo, chi, key);
-    const bool in_b = p < bhi && row_equal(b, k, p, key);
-    const bool in_c = q < chi && row_equal(c, k, q, key);
+    const bool in_b = in_window(b, k, wb, spb, S, key);
+    const bool in_c = in_window(c, k, wc, spc, S, key);
     flags[i] = (in_b || in_c) ? 0u : 1u;
   }
 }
@@ -750,8 +804,15 @@ u64 set_difference(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* 
   DBuf<u32> flags(c.mem, na);
   DBuf<u64> pos(c.mem, na), total(c.mem, 1);
   const ColsIn B = nb ? cols_in(k, b) : ColsIn{}, B2 = nb2 ? cols_in(k, b2) : ColsIn{};
-  k_absent_flags<<<grid_for(na, SEARCH_TILE), WG, 0, c.s>>>(A, B, B2, k, na, nb, nb2,
-                                                            flags.get());
+  const u32 S = AF_WORDS / (2 * k);
+  const u64 ntiles = ceil_div(na, (u64)SEARCH_TILE);
+  DBuf<u64> bb(c.mem, ntiles + 1), bc(c.mem, ntiles + 1);
+  k_tile_bounds<<<grid_for(ntiles + 1, WG), WG, 0, c.s>>>(A, B, k, na, nb, ntiles, bb.get());
+  WCDL_HIP(hipGetLastError());
+  k_tile_bounds<<<grid_for(ntiles + 1, WG), WG, 0, c.s>>>(A, B2, k, na, nb2, ntiles, bc.get());
+  WCDL_HIP(hipGetLastError());
+  k_absent_flags<<<(u32)ntiles, WG, (size_t)2 * S * k * sizeof(u32), c.s>>>(
+      A, B, B2, k, na, bb.get(), bc.get(), S, flags.get());
   WCDL_HIP(hipGetLastError());
   scan_u32_excl(c, flags.get(), pos.get(), na, total.get());
   k_compact<<<grid_for(na, WG), WG, 0, c.s>>>(A, cols_out(k, out), k, na, flags.get(), pos.get());
