@@ -309,12 +309,6 @@ __global__ __launch_bounds__(WG) void k_group_flags(ColsIn a, u32 kp, u64 n, u32
   flags[i] = f;
 }
 
-__global__ __launch_bounds__(WG) void k_group_starts(const u32* flags, const u64* pos, u64 n,
-                                                     u64* gs) {
-  const u64 i = (u64)blockIdx.x * WG + threadIdx.x;
-  if (i < n && flags[i]) gs[pos[i]] = i;
-}
-
 // Tile t = groups [t*G, (t+1)*G), `wpg` bitmap words each.  EMIT = false:
 // cnt[t] = the tile's unique rows.  EMIT = true: those rows, in order, from
 // off[t] on -- leading columns from the group's first row, last column from
@@ -447,12 +441,60 @@ __global__ __launch_bounds__(WG) void k_adjacent_flags(ColsIn a, u32 k, u64 n, u
   flags[i] = f;
 }
 
-__global__ __launch_bounds__(WG) void k_compact(ColsIn a, ColsOut o, u32 k, u64 n,
-                                                const u32* flags, const u64* pos) {
-  u64 i = (u64)blockIdx.x * WG + threadIdx.x;
-  if (i >= n || !flags[i]) return;
-  u64 p = pos[i];
-  for (u32 j = 0; j < k; ++j) o.c[j][p] = a.c[j][i];
+// Stream compaction in two passes over the flags, with no per-row positions:
+// per-tile counts (tiles of SCAN_TILE rows), a scan of those, then each tile
+// ranks its flagged rows itself.  Wave w of a tile owns rows
+// [w*64*SCAN_IPT, (w+1)*64*SCAN_IPT) of it, 64 consecutive rows per step, so
+// every load and store of a step is one contiguous run.
+__global__ __launch_bounds__(WG) void k_flag_tiles(const u32* flags, u64 n, u32* tcnt) {
+  __shared__ u64 sh[WG / 64];
+  const u64 base = (u64)blockIdx.x * SCAN_TILE + threadIdx.x;
+  u64 s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; ++i) {
+    const u64 r = base + (u64)i * WG;
+    if (r < n) s += flags[r] ? 1u : 0u;
+  }
+  u64 tot;
+  block_excl_scan(s, sh, &tot);
+  if (threadIdx.x == 0) tcnt[blockIdx.x] = (u32)tot;
+}
+
+// Flagged rows of a (or, with idx, their row numbers) in order, from
+// toff[tile] on.
+__global__ __launch_bounds__(WG) void k_compact_tiles(ColsIn a, ColsOut o, u32 k, u64 n,
+                                                      const u32* flags, const u64* toff,
+                                                      u64* idx) {
+  __shared__ u32 wc[WG / 64];
+  const u32 wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const u64 wbase = (u64)blockIdx.x * SCAN_TILE + (u64)wave * (64 * SCAN_IPT) + lane;
+  const u64 below = (1ull << lane) - 1ull;
+  u32 f[SCAN_IPT];
+  u32 cnt = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; ++i) {
+    const u64 r = wbase + (u64)i * 64;
+    f[i] = (r < n && flags[r]) ? 1u : 0u;
+    cnt += (u32)__popcll(__ballot(f[i]));
+  }
+  if (lane == 0) wc[wave] = cnt;
+  __syncthreads();
+  u64 at = toff[blockIdx.x];
+  for (u32 w = 0; w < wave; ++w) at += wc[w];
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; ++i) {
+    const u64 mask = __ballot(f[i]);
+    if (f[i]) {
+      const u64 r = wbase + (u64)i * 64;
+      const u64 p = at + (u64)__popcll(mask & below);
+      if (idx) {
+        idx[p] = r;
+      } else {
+        for (u32 j = 0; j < k; ++j) o.c[j][p] = a.c[j][r];
+      }
+    }
+    at += (u64)__popcll(mask);
+  }
 }
 
 // Splitters of a window [lo, hi) of b in LDS: row lo + j*stride for j < ns,
@@ -640,21 +682,55 @@ __global__ void k_lead_range(const u32* col, u64 n, u32 v, u64* out) {
 // ---------------------------------------------------------------------------
 // Launchers
 
+// Stream compaction by flags: count() scans the per-tile counts and returns
+// the flagged rows' number (synchronises), so the caller can size the output
+// exactly; write() puts the flagged rows of a in order into o (or their row
+// numbers into idx).
+struct FlagCompaction {
+  Ctx c;
+  const u32* flags;
+  u64 n, ntiles;
+  DBuf<u32> tcnt;
+  DBuf<u64> toff;
+  FlagCompaction(Ctx cx, const u32* f, u64 rows) : c(cx), flags(f), n(rows) {
+    ntiles = ceil_div(n, (u64)SCAN_TILE);
+    if (ntiles > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "compaction too large");
+    tcnt = DBuf<u32>(c.mem, ntiles);
+    toff = DBuf<u64>(c.mem, ntiles);
+  }
+  u64 count() {
+    DBuf<u64> total(c.mem, 1);
+    k_flag_tiles<<<(u32)ntiles, WG, 0, c.s>>>(flags, n, tcnt.get());
+    WCDL_HIP(hipGetLastError());
+    scan_u32_excl(c, tcnt.get(), toff.get(), ntiles, total.get());
+    u64 h = 0;
+    WCDL_HIP(hipMemcpyAsync(&h, total.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
+    WCDL_HIP(hipStreamSynchronize(c.s));
+    return h;
+  }
+  void write(u32 k, const ColsIn& a, const ColsOut& o, u64* idx) {
+    k_compact_tiles<<<(u32)ntiles, WG, 0, c.s>>>(a, o, k, n, flags, toff.get(), idx);
+    WCDL_HIP(hipGetLastError());
+  }
+};
+
+// Rows of a whose flag is set, in order, into o; returns their number once
+// they are written (synchronises: callers read the result from any stream).
+u64 compact_flagged(Ctx c, u32 k, const ColsIn& a, u64 n, const u32* flags, const ColsOut& o) {
+  FlagCompaction fc(c, flags, n);
+  const u64 h = fc.count();
+  if (h) fc.write(k, a, o, nullptr);
+  WCDL_HIP(hipStreamSynchronize(c.s));
+  return h;
+}
+
 u64 drop_leading(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32 lead_col, const u32* ids,
                  u64 nids, u32* const* out_cols) {
   if (n == 0) return 0;
   DBuf<u32> flags(c.mem, n);
-  DBuf<u64> pos(c.mem, n), total(c.mem, 1);
   k_keep_flags<<<grid_for(n, WG), WG, 0, c.s>>>(in_cols[lead_col], n, ids, nids, flags.get());
   WCDL_HIP(hipGetLastError());
-  scan_u32_excl(c, flags.get(), pos.get(), n, total.get());
-  k_compact<<<grid_for(n, WG), WG, 0, c.s>>>(cols_in(k, in_cols), cols_out(k, out_cols), k, n,
-                                              flags.get(), pos.get());
-  WCDL_HIP(hipGetLastError());
-  u64 h = 0;
-  WCDL_HIP(hipMemcpyAsync(&h, total.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
-  WCDL_HIP(hipStreamSynchronize(c.s));
-  return h;
+  return compact_flagged(c, k, cols_in(k, in_cols), n, flags.get(), cols_out(k, out_cols));
 }
 
 void lead_range(Ctx c, const u32* col, u64 n, u32 v, u64* d_out) {
@@ -741,22 +817,21 @@ bool sort_unique_grouped(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32 zbi
   if (n == 0) return true;
   const ColsIn A = cols_in(k, in_cols);
   DBuf<u32> flags(c.mem, n);
-  DBuf<u64> pos(c.mem, n), tot(c.mem, 1);
   k_group_flags<<<grid_for(n, WG), WG, 0, c.s>>>(A, k - 1, n, flags.get());
   WCDL_HIP(hipGetLastError());
-  scan_u32_excl(c, flags.get(), pos.get(), n, tot.get());
   u64 ng = 0;
-  WCDL_HIP(hipMemcpyAsync(&ng, tot.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
-  WCDL_HIP(hipStreamSynchronize(c.s));
+  DBuf<u64> gs;
   const u32 wpg = zbits <= 5 ? 1u : 1u << (zbits - 5);
-  // Each pass scans every group's bitmap: worth it while that is at most
-  // two words per row.
-  if (ng * wpg > 2 * n) return false;
-  DBuf<u64> gs(c.mem, ng);
-  k_group_starts<<<grid_for(n, WG), WG, 0, c.s>>>(flags.get(), pos.get(), n, gs.get());
-  WCDL_HIP(hipGetLastError());
+  {
+    FlagCompaction fc(c, flags.get(), n);
+    ng = fc.count();
+    // Each pass scans every group's bitmap: worth it while that is at most
+    // two words per row.
+    if (ng * wpg > 2 * n) return false;
+    gs = DBuf<u64>(c.mem, ng);  // group starts: row numbers of the flagged rows
+    fc.write(k, A, ColsOut{}, gs.get());
+  }
   flags = DBuf<u32>();
-  pos = DBuf<u64>();
   const u32 G = std::min<u32>(GB_GROUPS, GB_WORDS / wpg);
   const u64 ntiles = ceil_div(ng, (u64)G);
   if (ntiles > 0x7fffffffull) return false;
@@ -779,18 +854,10 @@ bool sort_unique_grouped(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32 zbi
 u64 unique_rows(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32* const* out_cols) {
   if (n == 0) return 0;
   DBuf<u32> flags(c.mem, n);
-  DBuf<u64> pos(c.mem, n), total(c.mem, 1);
   ColsIn a = cols_in(k, in_cols);
   k_adjacent_flags<<<grid_for(n, WG), WG, 0, c.s>>>(a, k, n, flags.get());
   WCDL_HIP(hipGetLastError());
-  scan_u32_excl(c, flags.get(), pos.get(), n, total.get());
-  k_compact<<<grid_for(n, WG), WG, 0, c.s>>>(a, cols_out(k, out_cols), k, n, flags.get(),
-                                              pos.get());
-  WCDL_HIP(hipGetLastError());
-  u64 h = 0;
-  WCDL_HIP(hipMemcpyAsync(&h, total.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
-  WCDL_HIP(hipStreamSynchronize(c.s));
-  return h;
+  return compact_flagged(c, k, a, n, flags.get(), cols_out(k, out_cols));
 }
 
 u64 set_difference(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* b, u64 nb,
@@ -802,7 +869,6 @@ u64 set_difference(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* 
     return na;
   }
   DBuf<u32> flags(c.mem, na);
-  DBuf<u64> pos(c.mem, na), total(c.mem, 1);
   const ColsIn B = nb ? cols_in(k, b) : ColsIn{}, B2 = nb2 ? cols_in(k, b2) : ColsIn{};
   const u32 S = AF_WORDS / (2 * k);
   const u64 ntiles = ceil_div(na, (u64)SEARCH_TILE);
@@ -814,13 +880,9 @@ u64 set_difference(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* 
   k_absent_flags<<<(u32)ntiles, WG, (size_t)2 * S * k * sizeof(u32), c.s>>>(
       A, B, B2, k, na, bb.get(), bc.get(), S, flags.get());
   WCDL_HIP(hipGetLastError());
-  scan_u32_excl(c, flags.get(), pos.get(), na, total.get());
-  k_compact<<<grid_for(na, WG), WG, 0, c.s>>>(A, cols_out(k, out), k, na, flags.get(), pos.get());
-  WCDL_HIP(hipGetLastError());
-  u64 h = 0;
-  WCDL_HIP(hipMemcpyAsync(&h, total.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
-  WCDL_HIP(hipStreamSynchronize(c.s));
-  return h;
+  bb = DBuf<u64>();
+  bc = DBuf<u64>();
+  return compact_flagged(c, k, A, na, flags.get(), cols_out(k, out));
 }
 
 void merge_disjoint(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* b, u64 nb,
