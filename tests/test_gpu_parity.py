@@ -420,6 +420,36 @@ def test_serve_release_and_live():
     e.close()
 
 
+def test_serve_live_lists_exactly_the_admitted_instances():
+    """The live set comes from distinct instance ids of the pending and delta
+    copies (a device dedup read back on the host): right after admission it
+    is exactly the admitted ids, and every step's list holds only those."""
+    rng = np.random.default_rng(5)
+    ids = np.sort(rng.choice(100_000, size=600, replace=False)).astype(np.uint32)
+    g = W.path_graph(200)
+    e = Engine(batched=True)
+    e.declare("edge", 2)
+    e.declare("path", 2)
+    e.add_rules(TC)
+    e.serve_begin()
+    e.serve_admit("edge", np.concatenate([np.concatenate([np.full((len(g), 1), i, np.uint32), g], axis=1)
+                                          for i in ids]).astype(np.uint32))
+    assert e.serve_live() == ids.tolist()
+    seen = 0
+    while True:
+        live = e.serve_live()
+        assert live == e.serve_live() and set(live) <= set(ids.tolist())
+        if not live:
+            break
+        e.serve_step()
+        seen += 1
+    assert seen > 1
+    for i in ids[:: 97]:
+        assert len(e.read_instance("path", int(i))) == 200 * 199 // 2
+    e.serve_end()
+    e.close()
+
+
 def test_split_q_through_ascending_triangles():
     """q(w,x,y,z) split with the helper H(w,x,z) :- edge(w,x), edge(x,z),
     edge(w,z): the implied w < x < z is pushed into the helper, q unchanged."""
