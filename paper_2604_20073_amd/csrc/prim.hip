@@ -416,8 +416,8 @@ __device__ inline u64 row_lower_bound(const ColsIn& b, u32 k, u64 lo, u64 hi,
 // bounds[ntiles] = nb: the rows of a's tile t can only equal rows of b in
 // [bounds[t], bounds[t+1]).  One thread per boundary, so the searches'
 // dependent loads overlap across the whole grid.
-__global__ __launch_bounds__(WG) void k_tile_bounds(ColsIn a, ColsIn b, u32 k, u64 na, u64 nb,
-                                                    u64 ntiles, u64* bounds) {
+__global__ __launch_bounds__(WG) void k_tile_bounds(ColsIn a, ColsIn b, u32 k, u64 nb, u64 ntiles,
+                                                    u64* bounds) {
   const u64 t = (u64)blockIdx.x * WG + threadIdx.x;
   if (t > ntiles) return;
   if (t == ntiles || nb == 0) {
@@ -873,9 +873,9 @@ u64 set_difference(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* 
   const u32 S = AF_WORDS / (2 * k);
   const u64 ntiles = ceil_div(na, (u64)SEARCH_TILE);
   DBuf<u64> bb(c.mem, ntiles + 1), bc(c.mem, ntiles + 1);
-  k_tile_bounds<<<grid_for(ntiles + 1, WG), WG, 0, c.s>>>(A, B, k, na, nb, ntiles, bb.get());
+  k_tile_bounds<<<grid_for(ntiles + 1, WG), WG, 0, c.s>>>(A, B, k, nb, ntiles, bb.get());
   WCDL_HIP(hipGetLastError());
-  k_tile_bounds<<<grid_for(ntiles + 1, WG), WG, 0, c.s>>>(A, B2, k, na, nb2, ntiles, bc.get());
+  k_tile_bounds<<<grid_for(ntiles + 1, WG), WG, 0, c.s>>>(A, B2, k, nb2, ntiles, bc.get());
   WCDL_HIP(hipGetLastError());
   k_absent_flags<<<(u32)ntiles, WG, (size_t)2 * S * k * sizeof(u32), c.s>>>(
       A, B, B2, k, na, bb.get(), bc.get(), S, flags.get());
