@@ -255,6 +255,41 @@ def test_least_model_brute_force(name):
         assert np.array_equal(res[n], as_sorted_array(model[n], ARITY[n])), n
 
 
+@pytest.mark.parametrize("op", ["<", "<=", ">", ">=", "!="])
+def test_comparison_operators_brute_force(op):
+    """Every comparison operator, both argument orders of the parser's
+    rewrite (> and >= swap their operands): the pairs of a small node set
+    that satisfy it, by enumeration."""
+    n = 9
+    nodes = np.arange(n, dtype=np.uint32)[:, None]
+    _, res = oracle.evaluate({"node": 1, "p": 2}, f"p(x,y) :- node(x), node(y), x {op} y.",
+                             {"node": nodes})
+    f = {"<": lambda a, b: a < b, "<=": lambda a, b: a <= b, ">": lambda a, b: a > b,
+         ">=": lambda a, b: a >= b, "!=": lambda a, b: a != b}[op]
+    expect = {(a, b) for a in range(n) for b in range(n) if f(a, b)}
+    assert np.array_equal(res["p"], as_sorted_array(expect, 2))
+
+
+def test_repeated_variables_within_an_atom_brute_force():
+    """A variable repeated inside one atom forces those columns equal:
+    self-loops, symmetric pairs through a repeated column of a ternary
+    relation, and a repeat that must agree with an earlier atom."""
+    rng = np.random.default_rng(11)
+    edges = np.unique(rng.integers(0, 6, size=(30, 2)), axis=0).astype(np.uint32)
+    tri = np.unique(rng.integers(0, 4, size=(40, 3)), axis=0).astype(np.uint32)
+    rules = ("loop(x) :- edge(x,x).\n"
+             "mid(x,y) :- t(x,y,x).\n"
+             "back(x,y) :- edge(x,y), t(y,x,x).")
+    _, res = oracle.evaluate({"edge": 2, "t": 3, "loop": 1, "mid": 2, "back": 2}, rules,
+                             {"edge": edges, "t": tri})
+    E = {tuple(map(int, r)) for r in edges}
+    T = {tuple(map(int, r)) for r in tri}
+    assert np.array_equal(res["loop"], as_sorted_array({(a,) for a, b in E if a == b}, 1))
+    assert np.array_equal(res["mid"], as_sorted_array({(a, b) for a, b, c in T if a == c}, 2))
+    expect = {(x, y) for x, y in E if (y, x, x) in T}
+    assert expect and np.array_equal(res["back"], as_sorted_array(expect, 2))
+
+
 def test_loaded_facts_in_head_relation_join_delta0():
     """Facts loaded into a derived relation are part of its first delta."""
     edges = W.path_graph(5)
