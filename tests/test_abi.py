@@ -47,6 +47,22 @@ def test_binding_lists_every_symbol():
     assert sorted(engine.EXPORTS) == declared_functions()
 
 
+def test_binding_flags_match_the_header():
+    """Every WCDL_F_* flag the header defines has the same value in the
+    Python binding and is exported by the package, and no two share a bit."""
+    import paper_2604_20073_amd as pkg
+    from paper_2604_20073_amd import engine
+    text = open(HEADER).read()
+    flags = {m.group(1): int(m.group(2), 16)
+             for m in re.finditer(r"#define\s+(WCDL_F_[A-Z_]+)\s+0x([0-9a-fA-F]+)u", text)}
+    assert len(flags) >= 8
+    for name, value in flags.items():
+        assert getattr(engine, name) == value, name
+        assert getattr(pkg, name) == value, name
+    values = sorted(flags.values())
+    assert all(v & (v - 1) == 0 for v in values) and len(set(values)) == len(values)
+
+
 def test_fig2_partition_golden():
     from paper_2604_20073_amd import owner_key, work_slice
     g = json.load(open(os.path.join(ROOT, "tests", "golden", "fig2_partition.json")))
