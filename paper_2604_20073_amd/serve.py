@@ -7,8 +7,9 @@ each kind on its own relations, every request being one instance.  The loop:
   1. move arrived requests into the queue;
   2. admit queued requests while the memory bound allows: resident rows plus
      the last step's count-pass bound (the rows its count passes reserved),
-     plus an allowance for the new request's input, must stay within the
-     budget; at most `max_active` requests run at once;
+     plus an allowance for the input of every request admitted since that
+     step (this one included), must stay within the budget; at most
+     `max_active` requests run at once;
   3. run one engine step (one semi-naive round for every live instance, all
      in the same launches);
   4. requests no longer live have reached their fixpoint: record completion,
@@ -80,6 +81,7 @@ class Server:
         nxt = 0
         last_bound = 0
         resident = 0
+        admitted_allow = 0     # allowances of requests admitted since the last step
         steps = 0
         t0 = time.perf_counter()
         while nxt < len(trace) or queue or active:
@@ -91,10 +93,11 @@ class Server:
             while queue and len(active) < self.max_active:
                 req = queue[0]
                 in_rows = sum(len(v) for v in facts[req["id"]].values())
-                need = (resident + last_bound + 8 * in_rows) * self.row_bytes
+                need = (resident + last_bound + admitted_allow + 8 * in_rows) * self.row_bytes
                 if active and need > self.budget:
                     break
                 queue.popleft()
+                admitted_allow += 8 * in_rows
                 for name, r in facts[req["id"]].items():
                     inst = np.concatenate([np.full((len(r), 1), req["id"], np.uint32),
                                            r.astype(np.uint32)], axis=1)
@@ -108,6 +111,7 @@ class Server:
             steps += 1
             last_bound = st["candidate_rows"]
             resident = st["resident_rows"]
+            admitted_allow = 0
             live = set(e.serve_live())
             t_done = time.perf_counter() - t0
             finished = [i for i in active if i not in live]
