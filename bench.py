@@ -340,7 +340,7 @@ def main():
                          "used to calibrate hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the engine on a single MI355X "
+        print("bench.py measures one GPU: the engine runs on a single MI355X "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 

@@ -115,3 +115,13 @@ def test_create_without_gpu_reports_device_error(lib):
     out = P()
     rc = lib.wcdl_create(None, ctypes.byref(out))
     assert rc != 0 and not out.value
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with a message
+    before touching any device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2 and "--gpus must be 1" in r.stderr
