@@ -4,9 +4,10 @@ Loads ``liboracle.so`` (built from ``oracle.cpp`` by :func:`build`) through
 ctypes.  Only the test suite, the smoke check and the benchmark's CPU-baseline
 leg use this package; the engine never imports it.
 
-The oracle computes the least model of a positive Datalog program by
-stratified semi-naive evaluation with pipelined nested-loop joins (paper
-Sec. 2); see the header of ``oracle.cpp`` for the exact round bookkeeping.
+The oracle computes the least (for stratified negation: perfect) model of a
+Datalog program by stratified semi-naive evaluation with pipelined
+nested-loop joins (paper Sec. 2); see the header of ``oracle.cpp`` for the
+exact round bookkeeping.
 """
 
 from __future__ import annotations

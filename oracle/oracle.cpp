@@ -5,10 +5,15 @@
 // the benchmark may load it; the engine itself never links, calls or falls
 // back to it.  It shares no code, header, table or helper with the engine.
 //
-// What it computes (paper Sec. 2, "Datalog"): the least model of a positive
-// Horn-clause program over the loaded facts, i.e. the smallest set of facts
-// that contains the inputs and is closed under every rule.  Shared variables
-// in a rule body act as equality constraints; comparisons are unsigned 32-bit.
+// What it computes (paper Sec. 2, "Datalog"): the least model of a Horn-clause
+// program over the loaded facts, i.e. the smallest set of facts that contains
+// the inputs and is closed under every rule.  Shared variables in a rule body
+// act as equality constraints; comparisons are unsigned 32-bit.  A body atom
+// written `!rel(...)` is negated (stratified negation, which the paper lists
+// among SRDatalog's features): its relation must lie in a strictly lower
+// stratum, every variable in it must occur in a positive body atom, and a
+// derivation survives only if that tuple is absent from the (complete)
+// relation -- the perfect model of a stratified program.
 //
 // How (paper Sec. 2):
 //   * relations are grouped into strongly connected components of the
@@ -36,8 +41,10 @@
 //
 // Parity pins (in the test suite): closed forms for paths, cycles and
 // complete graphs, BFS reachability and distance layers, matrix-product
-// triangle and 4-cycle counts, brute-force enumeration on tiny domains, a
-// naive per-round evaluator, and an independent points-to worklist solver.
+// triangle and 4-cycle counts, brute-force enumeration on tiny domains
+// (stratum by stratum, negation included), a naive per-round evaluator, and
+// an independent points-to worklist solver; mutated copies of this file must
+// each fail one of them.
 
 #include <algorithm>
 #include <chrono>
@@ -81,6 +88,7 @@ struct Cmp {
 struct Rule {
   Atom head;
   std::vector<Atom> body;
+  std::vector<Atom> negs;  // negated atoms: filters over lower strata
   std::vector<Cmp> cmps;
   u32 nvars = 0;
 };
@@ -272,6 +280,21 @@ int parse_program(oracle_prog* P, const std::string& src) {
     }
     if (!p.take(":-")) { P->err = "expected ':-' or '.'"; return -10; }
     for (;;) {
+      // A negated atom  !name(...)
+      if (p.take("!")) {
+        std::string nid;
+        if (!p.ident(nid) || !p.peek("(")) { P->err = "expected an atom after '!'"; return -10; }
+        auto jt = P->rel_ids.find(nid);
+        if (jt == P->rel_ids.end()) { P->err = "unknown relation " + nid; return -3; }
+        Atom a;
+        a.rel = jt->second;
+        if (!parse_atom_args(p, vars, r.nvars, a)) { P->err = p.err; return -10; }
+        if (a.t.size() != P->rels[a.rel].arity) { P->err = "arity mismatch in " + nid; return -2; }
+        r.negs.push_back(a);
+        if (p.take(".")) break;
+        if (!p.take(",")) { P->err = "expected ',' or '.'"; return -10; }
+        continue;
+      }
       // Either an atom  name(...)  or a comparison  term op term.
       size_t save = p.i;
       std::string id;
@@ -322,6 +345,12 @@ int parse_program(oracle_prog* P, const std::string& src) {
         P->err = "unsafe rule: unbound comparison variable";
         return -4;
       }
+    for (auto& a : r.negs)
+      for (auto& t : a.t)
+        if (t.is_var && !bound[t.v]) {
+          P->err = "unsafe rule: variable only in a negated atom";
+          return -4;
+        }
     P->rules.push_back(r);
   }
   return 0;
@@ -378,6 +407,18 @@ std::pair<u64, u64> probe(const Index& ix, const u32* key) {
   return {lo, lo2};
 }
 
+// Is `key` (arity values) a row of the sorted, unique tuple set?
+bool has_row(const TupleSet& ts, const u32* key) {
+  const u32 k = ts.arity;
+  u64 lo = 0, hi = ts.size();
+  while (lo < hi) {
+    const u64 mid = lo + (hi - lo) / 2;
+    const u32* r = ts.rows.data() + mid * k;
+    if (std::lexicographical_compare(r, r + k, key, key + k)) lo = mid + 1; else hi = mid;
+  }
+  return lo < ts.size() && std::equal(key, key + k, ts.rows.data() + lo * k);
+}
+
 bool cmp_holds(int op, u32 a, u32 b) {
   switch (op) {
     case LT: return a < b;
@@ -394,11 +435,12 @@ struct RulePlan {
   std::vector<int> cmps_first;                // comparisons over constants only
 };
 
-// Evaluate one rule with body atom i reading sources[i]; append head rows.
-// The body is joined in written order; `threads` > 1 splits the first atom's
-// matches across OpenMP threads (per-thread buffers joined in thread order).
+// Evaluate one rule with body atom i reading sources[i] and negated atom k
+// reading negsrc[k]; append head rows.  The body is joined in written order;
+// `threads` > 1 splits the first atom's matches across OpenMP threads
+// (per-thread buffers joined in thread order).
 void eval_rule(const Rule& r, const std::vector<const TupleSet*>& sources,
-               std::vector<u32>& out, int threads) {
+               const std::vector<const TupleSet*>& negsrc, std::vector<u32>& out, int threads) {
   const size_t na = r.body.size();
   RulePlan pl;
   pl.rule = &r;
@@ -469,7 +511,17 @@ void eval_rule(const Rule& r, const std::vector<const TupleSet*>& sources,
     const std::vector<std::vector<FreeCol>>& fc;
     std::vector<u32> val;
     std::vector<u32>* out;
+    const std::vector<const TupleSet*>& neg;
     u32 term_val(const Term& t) const { return t.is_var ? val[t.v] : t.v; }
+    // A derivation survives when no negated atom's tuple is present.
+    bool negs_absent() const {
+      u32 key[64];
+      for (size_t k = 0; k < r.negs.size(); ++k) {
+        for (size_t j = 0; j < r.negs[k].t.size(); ++j) key[j] = term_val(r.negs[k].t[j]);
+        if (has_row(*neg[k], key)) return false;
+      }
+      return true;
+    }
     bool bind(size_t i, const u32* row) {
       for (const FreeCol& f : fc[i]) {
         if (f.first) val[f.var] = row[f.j];
@@ -485,6 +537,7 @@ void eval_rule(const Rule& r, const std::vector<const TupleSet*>& sources,
       return true;
     }
     void emit() {
+      if (!negs_absent()) return;
       for (auto& t : r.head.t) out->push_back(term_val(t));
     }
     void walk(size_t i) {
@@ -514,7 +567,7 @@ void eval_rule(const Rule& r, const std::vector<const TupleSet*>& sources,
 #ifdef _OPENMP
     tid = omp_get_thread_num();
 #endif
-    Walker w{r, pl, freecols, std::vector<u32>(r.nvars, 0), &bufs[tid]};
+    Walker w{r, pl, freecols, std::vector<u32>(r.nvars, 0), &bufs[tid], negsrc};
     // Static contiguous split: thread t takes a contiguous block of rows, so
     // joining the buffers in thread order reproduces the sequential order.
     u64 n = hi - lo, per = (n + nt - 1) / nt;
@@ -540,8 +593,10 @@ void eval_rule(const Rule& r, const std::vector<const TupleSet*>& sources,
 std::vector<std::vector<int>> strata(const oracle_prog* P) {
   const int n = (int)P->rels.size();
   std::vector<std::vector<int>> dep(n);
-  for (auto& r : P->rules)
+  for (auto& r : P->rules) {
     for (auto& a : r.body) dep[r.head.rel].push_back(a.rel);
+    for (auto& a : r.negs) dep[r.head.rel].push_back(a.rel);
+  }
   // Tarjan's algorithm (iterative bookkeeping kept simple with recursion;
   // programs here have few relations).
   std::vector<int> index(n, -1), low(n, 0), stack;
@@ -590,6 +645,20 @@ std::vector<std::vector<int>> strata(const oracle_prog* P) {
 }
 
 int run_program(oracle_prog* P, int threads) {
+  // Stratification: a negated relation must be finished before the rule's
+  // head is computed, i.e. lie in another (hence lower) component.
+  {
+    auto cs = strata(P);
+    std::vector<size_t> comp_of(P->rels.size(), 0);
+    for (size_t ci = 0; ci < cs.size(); ++ci)
+      for (int x : cs[ci]) comp_of[x] = ci;
+    for (auto& r : P->rules)
+      for (auto& a : r.negs)
+        if (comp_of[a.rel] == comp_of[r.head.rel]) {
+          P->err = "program not stratifiable: negation inside a recursive component";
+          return -5;
+        }
+  }
   for (size_t r = 0; r < P->rels.size(); ++r) {
     auto& rel = P->rels[r];
     auto& pf = P->pending_facts[r];
@@ -615,9 +684,10 @@ int run_program(oracle_prog* P, int threads) {
     // Exit rules read only finished relations.
     std::map<int, std::vector<u32>> fresh;
     for (const Rule* r : exit_rules) {
-      std::vector<const TupleSet*> src;
+      std::vector<const TupleSet*> src, nsrc;
       for (auto& a : r->body) src.push_back(&P->rels[a.rel].full);
-      eval_rule(*r, src, fresh[r->head.rel], threads);
+      for (auto& a : r->negs) nsrc.push_back(&P->rels[a.rel].full);
+      eval_rule(*r, src, nsrc, fresh[r->head.rel], threads);
     }
     for (auto& kv : fresh) {
       auto& rel = P->rels[kv.first];
@@ -641,7 +711,9 @@ int run_program(oracle_prog* P, int threads) {
             int rel = r->body[i].rel;
             src.push_back(i == j ? &delta[rel] : &P->rels[rel].full);
           }
-          eval_rule(*r, src, cand[r->head.rel], threads);
+          std::vector<const TupleSet*> nsrc;
+          for (auto& a : r->negs) nsrc.push_back(&P->rels[a.rel].full);
+          eval_rule(*r, src, nsrc, cand[r->head.rel], threads);
         }
       }
       bool any = false;

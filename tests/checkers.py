@@ -16,7 +16,11 @@ Rules are given as Python structures, rendered to the text syntax with
 
     Rule(head=("path", ("x", "z")),
          body=[("path", ("x", "y")), ("edge", ("y", "z"))],
-         cmps=[("<", "x", "z")])
+         cmps=[("<", "x", "z")],
+         negs=[("blocked", ("x", "z"))])       # rendered as !blocked(x, z)
+
+Negated atoms read relations of lower strata; every checker evaluates the
+strata in dependency order, so a negated relation is complete when read.
 
 A term is a variable name (str) or a constant (int).
 """
@@ -35,6 +39,7 @@ class Rule:
     head: tuple
     body: list
     cmps: list = field(default_factory=list)
+    negs: list = field(default_factory=list)
 
 
 def _term(t):
@@ -46,6 +51,7 @@ def render(rules) -> str:
     for r in rules:
         h = f"{r.head[0]}({', '.join(_term(t) for t in r.head[1])})"
         items = [f"{a[0]}({', '.join(_term(t) for t in a[1])})" for a in r.body]
+        items += [f"!{a[0]}({', '.join(_term(t) for t in a[1])})" for a in r.negs]
         items += [f"{_term(a)} {op} {_term(b)}" for op, a, b in r.cmps]
         lines.append(f"{h} :- {', '.join(items)}.")
     return "\n".join(lines)
@@ -91,8 +97,12 @@ def _eval_rule_hash(rule, rels):
         envs = nxt
     out = set()
     for env in envs:
-        if all(_OPS[op](_val(a, env), _val(b, env)) for op, a, b in rule.cmps):
-            out.add(tuple(_val(t, env) for t in rule.head[1]))
+        if not all(_OPS[op](_val(a, env), _val(b, env)) for op, a, b in rule.cmps):
+            continue
+        if any(tuple(_val(t, env) for t in terms) in rels.get(name, set())
+               for name, terms in rule.negs):
+            continue
+        out.add(tuple(_val(t, env) for t in rule.head[1]))
     return out
 
 
@@ -100,7 +110,7 @@ def _sccs(rules, names):
     """Strongly connected components, dependencies first (Kosaraju)."""
     g = defaultdict(set)
     for r in rules:
-        for a in r.body:
+        for a in list(r.body) + list(r.negs):
             g[r.head[0]].add(a[0])
     order, seen = [], set()
 
@@ -181,33 +191,38 @@ def naive_rounds(rules, facts: dict, names) -> tuple:
 
 
 def brute_force(rules, facts: dict, names, consts=()) -> dict:
-    """Least model by repeated enumeration of every variable assignment over
-    the active domain until nothing changes (tiny inputs only)."""
+    """Least (perfect) model by repeated enumeration of every variable
+    assignment over the active domain until nothing changes, one stratum at
+    a time in dependency order (tiny inputs only)."""
     rels = {n: set(map(tuple, np.asarray(facts.get(n, np.zeros((0, 0)))).tolist())) for n in names}
     dom = set(consts)
     for s in rels.values():
         for t in s:
             dom.update(t)
     for r in rules:
-        for a in r.body:
+        for a in list(r.body) + list(r.negs):
             dom.update(t for t in a[1] if isinstance(t, int))
         dom.update(t for t in r.head[1] if isinstance(t, int))
     dom = sorted(dom)
-    changed = True
-    while changed:
-        changed = False
-        for r in rules:
-            vs = sorted({t for a in r.body for t in a[1] if isinstance(t, str)})
-            for vals in itertools.product(dom, repeat=len(vs)):
-                env = dict(zip(vs, vals))
-                if not all(tuple(_val(t, env) for t in a[1]) in rels[a[0]] for a in r.body):
-                    continue
-                if not all(_OPS[op](_val(a, env), _val(b, env)) for op, a, b in r.cmps):
-                    continue
-                h = tuple(_val(t, env) for t in r.head[1])
-                if h not in rels[r.head[0]]:
-                    rels[r.head[0]].add(h)
-                    changed = True
+    for comp in _sccs(rules, names):
+        mine = [r for r in rules if r.head[0] in comp]
+        changed = True
+        while changed:
+            changed = False
+            for r in mine:
+                vs = sorted({t for a in r.body for t in a[1] if isinstance(t, str)})
+                for vals in itertools.product(dom, repeat=len(vs)):
+                    env = dict(zip(vs, vals))
+                    if not all(tuple(_val(t, env) for t in a[1]) in rels[a[0]] for a in r.body):
+                        continue
+                    if not all(_OPS[op](_val(a, env), _val(b, env)) for op, a, b in r.cmps):
+                        continue
+                    if any(tuple(_val(t, env) for t in a[1]) in rels[a[0]] for a in r.negs):
+                        continue
+                    h = tuple(_val(t, env) for t in r.head[1])
+                    if h not in rels[r.head[0]]:
+                        rels[r.head[0]].add(h)
+                        changed = True
     return rels
 
 

@@ -58,6 +58,12 @@ MUTANTS = [
     ("exit_results_dropped",
      "rel.full.rows = set_union(rel.arity, rel.full.rows, kv.second);",
      "(void)kv;"),
+    ("negated_atoms_ignored",
+     "if (!negs_absent()) return;",
+     "(void)0;"),
+    ("negation_not_a_dependency",
+     "    for (auto& a : r.negs) dep[r.head.rel].push_back(a.rel);\n",
+     ""),
     ("difference_matches_first_column_only",
      "if (j < nb && std::equal(ra, ra + arity, b.data() + j * arity)) continue;",
      "if (j < nb && std::equal(ra, ra + 1, b.data() + j * arity)) continue;"),

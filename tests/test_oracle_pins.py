@@ -290,6 +290,93 @@ def test_repeated_variables_within_an_atom_brute_force():
     assert expect and np.array_equal(res["back"], as_sorted_array(expect, 2))
 
 
+# --------------------------------------------------------------------------
+# Stratified negation (a negated atom reads a relation of a lower stratum)
+# --------------------------------------------------------------------------
+
+_NODE = [Rule(("node", ("x",)), [("edge", ("x", "y"))]),
+         Rule(("node", ("y",)), [("edge", ("x", "y"))])]
+NEG_PROGRAMS = {
+    "unreach": _NODE + [
+        Rule(("path", ("x", "y")), [("edge", ("x", "y"))]),
+        Rule(("path", ("x", "z")), [("path", ("x", "y")), ("edge", ("y", "z"))]),
+        Rule(("un", ("x", "y")), [("node", ("x",)), ("node", ("y",))], negs=[("path", ("x", "y"))])],
+    "layered": _NODE + [
+        Rule(("hasout", ("x",)), [("edge", ("x", "y"))]),
+        Rule(("sinkn", ("x",)), [("node", ("x",))], negs=[("hasout", ("x",))]),
+        Rule(("rs", ("x", "y")), [("edge", ("x", "y")), ("sinkn", ("y",))]),
+        Rule(("rs", ("x", "z")), [("edge", ("x", "y")), ("rs", ("y", "z"))]),
+        Rule(("reachs", ("x",)), [("rs", ("x", "y"))]),
+        Rule(("lonely", ("x",)), [("node", ("x",))], negs=[("reachs", ("x",))])],
+    "consts_cmps": _NODE + [
+        Rule(("nonedge", ("x", "y")), [("node", ("x",)), ("node", ("y",))], [("<", "x", "y")],
+             negs=[("edge", ("x", "y")), ("edge", ("y", "x"))]),
+        Rule(("notfrom0", ("y",)), [("node", ("y",))], negs=[("edge", (0, "y"))])],
+    "recursive_filter": _NODE + [
+        Rule(("bad", ("x",)), [("node", ("x",))], [("<", "x", 3)]),
+        Rule(("sp", ("x", "y")), [("edge", ("x", "y"))], negs=[("bad", ("y",))]),
+        Rule(("sp", ("x", "z")), [("sp", ("x", "y")), ("edge", ("y", "z"))], negs=[("bad", ("z",))])],
+}
+NEG_ARITY = {"edge": 2, "node": 1, "path": 2, "un": 2, "hasout": 1, "sinkn": 1, "rs": 2,
+             "reachs": 1, "lonely": 1, "nonedge": 2, "notfrom0": 1, "bad": 1, "sp": 2}
+
+
+def _names(rules):
+    return sorted({r.head[0] for r in rules} | {a[0] for r in rules for a in r.body}
+                  | {a[0] for r in rules for a in r.negs})
+
+
+@pytest.mark.parametrize("name", sorted(NEG_PROGRAMS))
+@pytest.mark.parametrize("seed", range(3))
+def test_negation_semi_naive_equals_naive_rounds(name, seed):
+    rules = NEG_PROGRAMS[name]
+    names = _names(rules)
+    edges = W.er_graph(12, 20, 700 + seed)
+    o, res = oracle.evaluate({n: NEG_ARITY[n] for n in names}, render(rules), {"edge": edges})
+    model, deltas = naive_rounds(rules, {"edge": edges}, names)
+    for n in names:
+        assert np.array_equal(res[n], as_sorted_array(model[n], NEG_ARITY[n])), n
+    for n, d in deltas.items():
+        assert o.delta_sizes(n) == d, n
+
+
+@pytest.mark.parametrize("name", sorted(NEG_PROGRAMS))
+def test_negation_brute_force(name):
+    rules = NEG_PROGRAMS[name]
+    names = _names(rules)
+    edges = W.er_graph(6, 8, 78)
+    _, res = oracle.evaluate({n: NEG_ARITY[n] for n in names}, render(rules), {"edge": edges})
+    model = brute_force(rules, {"edge": edges}, names)
+    for n in names:
+        assert np.array_equal(res[n], as_sorted_array(model[n], NEG_ARITY[n])), n
+
+
+def test_negation_complement_of_closure():
+    """On the path 0 -> ... -> n-1 the closure is {x < y}, so the pairs of
+    nodes not connected are exactly {x >= y}."""
+    n = 9
+    rules = NEG_PROGRAMS["unreach"]
+    _, res = oracle.evaluate({m: NEG_ARITY[m] for m in _names(rules)}, render(rules),
+                             {"edge": W.path_graph(n)})
+    expect = {(x, y) for x in range(n) for y in range(n) if x >= y}
+    assert np.array_equal(res["un"], as_sorted_array(expect, 2))
+
+
+def test_negation_rejects_unstratifiable_and_unsafe():
+    for text in ["p(x) :- node(x), !p(x).",
+                 "p(x) :- node(x), !q(x).\nq(x) :- node(x), !p(x).",
+                 "p(x) :- node(x), q(x).\nq(x) :- p(x), !p(x)."]:
+        o = oracle.Oracle({"node": 1, "p": 1, "q": 1})
+        o.add_rules(text)
+        o.load("node", np.arange(3, dtype=np.uint32)[:, None])
+        with pytest.raises(oracle.OracleError, match="stratifiable"):
+            o.run()
+    for text in ["p(x) :- node(x), !e(x,y).", "p(x) :- node(x), !x < 2.", "p(x) :- !node(x)."]:
+        o = oracle.Oracle({"node": 1, "p": 1, "e": 2})
+        with pytest.raises(oracle.OracleError):
+            o.add_rules(text)
+
+
 def test_loaded_facts_in_head_relation_join_delta0():
     """Facts loaded into a derived relation are part of its first delta."""
     edges = W.path_graph(5)
