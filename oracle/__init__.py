@@ -24,6 +24,10 @@ _SRC = os.path.join(_HERE, "oracle.cpp")
 # load deliberately broken copies through it, each in its own process).
 _LIB = os.environ.get("ORACLE_LIB_PATH") or os.path.join(_HERE, "liboracle.so")
 _lib = None
+# Threads used by run() and evaluate() when the caller names none.  The pin
+# suite runs every pin with 1 and with several threads, so the threaded mode
+# is pinned by the same facts as the sequential one.
+DEFAULT_THREADS = 1
 
 
 def build(force: bool = True) -> str:
@@ -59,6 +63,8 @@ def _load():
     lib.oracle_rounds.restype = ctypes.c_uint64
     lib.oracle_delta_sizes.argtypes = [P, ctypes.c_char_p, ctypes.c_void_p, ctypes.c_uint64]
     lib.oracle_delta_sizes.restype = ctypes.c_uint64
+    lib.oracle_set_flush_rows.argtypes = [ctypes.c_uint64]
+    lib.oracle_set_flush_rows.restype = None
     _lib = lib
     return lib
 
@@ -103,7 +109,9 @@ class Oracle:
             a = a.reshape(-1, k)
         self._check(self._lib.oracle_load(self._p, name.encode(), a.ctypes.data, a.shape[0]))
 
-    def run(self, threads: int = 1) -> float:
+    def run(self, threads: int | None = None) -> float:
+        if threads is None:
+            threads = DEFAULT_THREADS
         s = ctypes.c_double(0.0)
         self._check(self._lib.oracle_run(self._p, int(threads), ctypes.byref(s)))
         self.seconds = s.value
@@ -130,7 +138,13 @@ class Oracle:
         return [int(x) for x in buf[:n]]
 
 
-def evaluate(relations: dict, rules: str, facts: dict, threads: int = 1):
+def set_flush_rows(rows: int) -> None:
+    """Rows a thread buffers before deduplicating them early (0 = default
+    2^24); tests lower it so that small inputs exercise that path."""
+    _load().oracle_set_flush_rows(int(rows))
+
+
+def evaluate(relations: dict, rules: str, facts: dict, threads: int | None = None):
     """Convenience: run a program and return (oracle, {name: rows})."""
     o = Oracle(relations)
     o.add_rules(rules)

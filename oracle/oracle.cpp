@@ -435,6 +435,10 @@ struct RulePlan {
   std::vector<int> cmps_first;                // comparisons over constants only
 };
 
+// Rows a thread buffers before deduplicating them early.  A test hook lowers
+// it so that small inputs exercise the early deduplication.
+u64 g_flush_rows = 1ull << 24;
+
 // Evaluate one rule with body atom i reading sources[i] and negated atom k
 // reading negsrc[k]; append head rows.  The body is joined in written order;
 // `threads` > 1 splits the first atom's matches across OpenMP threads
@@ -572,13 +576,16 @@ void eval_rule(const Rule& r, const std::vector<const TupleSet*>& sources,
     // joining the buffers in thread order reproduces the sequential order.
     u64 n = hi - lo, per = (n + nt - 1) / nt;
     u64 b = lo + std::min<u64>(n, per * tid), e = lo + std::min<u64>(n, per * (tid + 1));
-    const u64 flush_rows = 1ull << 24;
+    const u64 ha = r.head.t.size();
+    u64 limit = g_flush_rows;
     for (u64 k = b; k < e; ++k) {
       if (w.bind(0, ix0.rows.data() + k * ix0.arity) && w.cmps_ok(0)) w.walk(1);
       // Keep per-thread candidate buffers bounded: deduplicating early does
-      // not change the set that is produced.
-      if (r.head.t.size() && bufs[tid].size() / r.head.t.size() > flush_rows) {
-        sort_unique((u32)r.head.t.size(), bufs[tid]);
+      // not change the set that is produced.  The next flush waits until the
+      // buffer has doubled past its deduplicated size.
+      if (ha && bufs[tid].size() / ha > limit) {
+        sort_unique((u32)ha, bufs[tid]);
+        limit = std::max<u64>(g_flush_rows, 2 * (bufs[tid].size() / ha));
       }
     }
   }
@@ -810,6 +817,10 @@ int oracle_read(const oracle_prog* P, const char* name, uint32_t* out) {
 }
 
 uint64_t oracle_rounds(const oracle_prog* P) { return P->rounds; }
+
+// Test hook: per-thread rows buffered before an early deduplication (0 restores
+// the default of 2^24).
+void oracle_set_flush_rows(uint64_t rows) { g_flush_rows = rows ? rows : (1ull << 24); }
 
 // Writes up to cap delta sizes of the relation; returns how many exist.
 uint64_t oracle_delta_sizes(const oracle_prog* P, const char* name, uint64_t* out, uint64_t cap) {

@@ -2,8 +2,10 @@
 
 Each mutant is a copy of ``oracle/oracle.cpp`` with one deliberate slip -- a
 dropped term, a wrong index or bound, a swapped operand, a skipped step --
-compiled into a scratch library and loaded (through ``ORACLE_LIB_PATH``) by
-the pin suite ``tests/test_oracle_pins.py`` in a process of its own.  Every
+compiled (with OpenMP, as the oracle itself is) into a scratch library and
+loaded (through ``ORACLE_LIB_PATH``) by the pin suite
+``tests/test_oracle_pins.py`` in a process of its own; that suite runs every
+pin with the sequential and with the threaded evaluation.  Every
 mutant must fail at least one pin; the unmutated source, compiled the same
 way, must pass them all (so a broken harness cannot pass as "detected").
 """
@@ -64,6 +66,18 @@ MUTANTS = [
     ("negation_not_a_dependency",
      "    for (auto& a : r.negs) dep[r.head.rel].push_back(a.rel);\n",
      ""),
+    # Slips in the threaded mode (only the pins run with several threads
+    # reach them): a thread block that stops one row early, the buffers of
+    # the other threads dropped, an early deduplication with the wrong arity.
+    ("thread_block_drops_last_row",
+     "e = lo + std::min<u64>(n, per * (tid + 1));",
+     "e = lo + std::min<u64>(n, per * (tid + 1) - (tid + 1 < nt ? 1 : 0));"),
+    ("first_thread_buffer_only",
+     "for (auto& b : bufs) out.insert(out.end(), b.begin(), b.end());",
+     "out.insert(out.end(), bufs[0].begin(), bufs[0].end());"),
+    ("early_dedup_wrong_arity",
+     "sort_unique((u32)ha, bufs[tid]);",
+     "sort_unique(1, bufs[tid]);"),
     ("difference_matches_first_column_only",
      "if (j < nb && std::equal(ra, ra + arity, b.data() + j * arity)) continue;",
      "if (j < nb && std::equal(ra, ra + 1, b.data() + j * arity)) continue;"),
@@ -85,7 +99,7 @@ def builds(tmp_path_factory):
         cpp = d / f"{name}.cpp"
         cpp.write_text(text)
         libs[name] = str(d / f"lib{name}.so")
-        procs[name] = subprocess.Popen(["g++", "-std=c++17", "-O1", "-shared", "-fPIC", "-o",
+        procs[name] = subprocess.Popen(["g++", "-std=c++17", "-O1", "-fopenmp", "-shared", "-fPIC", "-o",
                                         libs[name], str(cpp)], stderr=subprocess.PIPE)
     for name, p in procs.items():
         _, err = p.communicate()

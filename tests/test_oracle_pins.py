@@ -38,6 +38,18 @@ pt(v,h) :- load(v,p), pt(p,q), pt(q,h).
 pt(q,h) :- store(p,w), pt(p,q), pt(w,h)."""
 
 
+@pytest.fixture(autouse=True, params=[1, 4], ids=["seq", "omp4"])
+def oracle_threads(request):
+    """Every pin runs twice: with the oracle's sequential evaluation and with
+    its threaded mode (4 threads, each deduplicating its buffer early after
+    every few rows), so the threaded mode is pinned by the same facts."""
+    oracle.DEFAULT_THREADS = request.param
+    oracle.set_flush_rows(3 if request.param > 1 else 0)
+    yield request.param
+    oracle.DEFAULT_THREADS = 1
+    oracle.set_flush_rows(0)
+
+
 def run_tc(edges):
     o, res = oracle.evaluate({"edge": 2, "path": 2}, TC, {"edge": edges})
     return o, res["path"]
@@ -450,3 +462,30 @@ def test_4clique_through_shared_triangle_helper_same_model(seed):
                         cliques.add((w, x, y, z))
     assert np.array_equal(plain["q"], as_sorted_array(cliques, 4))
     assert len(cliques) > 0
+
+
+@pytest.mark.parametrize("program", ["tc", "tri_q", "andersen"])
+def test_threaded_oracle_equals_sequential(program, oracle_threads):
+    """The threaded mode splits the outermost atom's matches into contiguous
+    blocks, one per thread, with per-thread buffers deduplicated early; rows,
+    per-round deltas and the round count must equal the sequential mode's at
+    every thread count (blocks of unequal length, more threads than rows)."""
+    if oracle_threads != 1:
+        pytest.skip("compares thread counts itself")
+    if program == "tc":
+        rels, rules, facts = {"edge": 2, "path": 2}, TC, {"edge": W.er_graph(300, 900, 17)}
+    elif program == "tri_q":
+        rels, rules = {"edge": 2, "tri": 3, "q": 4}, TRI + "\n" + Q4
+        facts = {"edge": W.rmat_graph(10, 7000, 18)}
+    else:
+        rels = {"addressOf": 2, "assign": 2, "load": 2, "store": 2, "pt": 2}
+        rules, facts = ANDERSEN, W.andersen_scaled(W.SEED_BASE + 2, 0.0005)
+    o1, r1 = oracle.evaluate(rels, rules, facts, threads=1)
+    for threads, flush in [(4, 0), (7, 5), (64, 2)]:
+        oracle.set_flush_rows(flush)
+        ot, rt = oracle.evaluate(rels, rules, facts, threads=threads)
+        oracle.set_flush_rows(0)
+        for n in rels:
+            assert np.array_equal(rt[n], r1[n]), (threads, n)
+            assert ot.delta_sizes(n) == o1.delta_sizes(n), (threads, n)
+        assert ot.rounds == o1.rounds
