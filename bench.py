@@ -69,10 +69,12 @@ def profiled_traffic(kernel: str, workload: str):
     return int(rec["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(edges: np.ndarray, target_s: float, threads: int) -> dict:
+def cpu_baseline(edges: np.ndarray, target_s: float, threads: int):
     """The CPU oracle on a bounded sample: the same two rules with the
     outermost atom restricted to the edges of a random sample of source
-    nodes.  Returns derived tuples/s of that sample."""
+    nodes.  Returns derived tuples/s of that sample, the sampled sources and
+    the oracle's tri and q rows for them (rows whose first column is a
+    sampled source)."""
     import oracle
     from paper_2604_20073_amd import workloads as W
 
@@ -94,14 +96,26 @@ def cpu_baseline(edges: np.ndarray, target_s: float, threads: int) -> dict:
         o.run(threads)
         secs = time.perf_counter() - t0
         rows = o.size("tri") + o.size("q")
-        last = dict(value=rows / secs, unit="tuples/s", cores=threads, kind="oracle",
-                    sample=(f"rules restricted to the out-edges of {int(pick.sum())} random source "
-                            f"nodes ({keep.sum()} edges, {frac:.6f} of the sources); "
-                            f"{rows} derived tuples in {secs:.2f} s"))
+        last = (dict(value=rows / secs, unit="tuples/s", cores=threads, kind="oracle",
+                     sample=(f"rules restricted to the out-edges of {int(pick.sum())} random "
+                             f"source nodes ({keep.sum()} edges, {frac:.6f} of the sources); "
+                             f"{rows} derived tuples in {secs:.2f} s")),
+                src[pick], o)
         if secs >= 10.0 or frac >= 1.0:
             break
         frac = min(1.0, frac * max(2.0, min(8.0, target_s / max(secs, 1e-3))))
-    return last
+    base, sources, o = last
+    return base, sources, o.read("tri"), o.read("q")
+
+
+def rows_with_leads(e, name: str, leads) -> np.ndarray:
+    """The engine's rows whose first column is one of `leads` (ascending)."""
+    parts = []
+    for s in leads:
+        first, n = e.range(name, int(s))
+        if n:
+            parts.append(e.read_rows_numpy(name, first, n))
+    return np.concatenate(parts) if parts else np.zeros((0, e.arity[name]), np.uint32)
 
 
 ANDERSEN = """pt(v,h) :- addressOf(v,h).
@@ -435,11 +449,18 @@ def main():
     kernels = {k: round(sum(s["kernel_ms"][k] for s in stats) / args.steps, 2)
                for k in stats[0]["kernel_ms"]}
 
-    base = None
+    base, parity = None, None
     if not args.no_cpu_baseline:
         threads = len(os.sched_getaffinity(0))
         log(f"cpu baseline on {threads} threads")
-        base = cpu_baseline(edges, args.cpu_seconds, threads)
+        base, sources, tri_o, q_o = cpu_baseline(edges, args.cpu_seconds, threads)
+        # The engine's rows for the sampled sources must equal the oracle's.
+        tri_g = rows_with_leads(e, "tri", sources)
+        q_g = rows_with_leads(e, "q", sources)
+        ok = bool(np.array_equal(tri_g, tri_o) and np.array_equal(q_g, q_o))
+        parity = {"sources": int(len(sources)), "tri_rows": int(len(tri_o)),
+                  "q_rows": int(len(q_o)), "match": ok}
+        log(f"sampled parity: {parity}")
 
     out = {
         "metric": "derived tuples/sec to fixpoint + HBM GB/s",
@@ -461,6 +482,7 @@ def main():
                    "tri": n_tri, "q": n_q, "derived": derived},
         "roofline": roofline,
         "cpu_baseline": base,
+        "sample_parity": parity,
         "phase_ms": phases,
         "kernel_ms": kernels,
         "candidates_per_level": [x // args.steps for x in
@@ -468,6 +490,9 @@ def main():
     }
     print(json.dumps(out), flush=True)
     e.close()
+    if parity is not None and not parity["match"]:
+        log("sampled rows differ from the oracle's")
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -115,9 +115,21 @@ typedef struct {
   void* const* streams;      /* hipStream_t handles owned by the caller; stream 0 is
                                 the main stream (all default priority) */
   wcdl_allocator alloc;      /* see above */
-  uint64_t mem_budget_bytes; /* 0 = unlimited; otherwise a rule version whose
-                                count-pass output would exceed it fails the run
-                                with WCDL_E_BUDGET */
+  uint64_t mem_budget_bytes; /* 0 = unlimited.  Otherwise a bound on the device
+                                memory held by the relations (every stored copy:
+                                loaded facts, the full relation, its other column
+                                orders, deltas; rows x stored arity x 4 bytes)
+                                together with one round's candidate rows.  After
+                                a round's count pass (Alg. 1 Phase 2), if the
+                                rows it counted (x head arity x 4 bytes, before
+                                deduplication) do not fit beside the relations
+                                within the bound, the run fails with
+                                WCDL_E_BUDGET before anything of that round is
+                                written: the relations keep the last completed
+                                round and the engine stays usable.  The count
+                                pass's staging arena is also held within the
+                                bound.  Kernel scratch (sort buffers, histograms,
+                                root keys) is not counted. */
   uint32_t flags;            /* WCDL_F_* */
   uint32_t wg_per_cu;        /* work-partition oversubscription: p = 256 CUs x
                                 wg_per_cu workgroups per join; 0 = default (32) */
@@ -125,6 +137,12 @@ typedef struct {
                                 a rule version produced per work unit last time
                                 (0 = default 125).  Rows that do not fit are
                                 recomputed by the write pass. */
+  uint64_t chunk_bytes;      /* candidate rows of one head relation written at
+                                once (Alg. 1 Phase 3): larger outputs are written
+                                in ranges of workgroups, each range deduplicated
+                                and subtracted before the next is written (0 =
+                                6 % of device memory).  Fails with WCDL_E_BUDGET
+                                if one work unit alone produces more. */
 } wcdl_config;
 
 /* Fill `cfg` with defaults (device 0, own streams, hipMalloc, no budget). */
@@ -277,8 +295,10 @@ typedef struct {
 /* Evaluate every stratum to its fixpoint (Sec. 2 stratification; the loop of
  * Sec. 4 stops when the deduplicated delta is empty).  Derived relations are
  * recomputed from the loaded facts on every call.  stats may be NULL.  On
- * WCDL_E_BUDGET or WCDL_E_NOMEM the derived relations keep the last completed
- * round and the engine stays usable. */
+ * WCDL_E_BUDGET (see wcdl_config.mem_budget_bytes) the relations hold the
+ * state after the last completed round of the stratum that failed (earlier
+ * strata complete, later ones as loaded), reads return that state, and the
+ * engine stays usable: a later run recomputes from the loaded facts. */
 wcdl_status wcdl_run(wcdl_engine* e, wcdl_run_stats* stats);
 
 /* Rows currently held by a relation (after wcdl_run: its least-model size). */

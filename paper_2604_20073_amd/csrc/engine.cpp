@@ -1032,6 +1032,19 @@ void repartition(Engine* e, VRun& R, u64 max_rows, Stats& st) {
   }
 }
 
+// Device bytes held by every stored copy of every relation (loaded facts,
+// full relation and head run, other column orders, deltas).
+u64 resident_bytes(const Engine* e) {
+  u64 b = 0;
+  for (const auto& R : e->rels) {
+    u64 rows = R.base.n + R.full.n + R.head.n;
+    for (const auto& kv : R.full_ord) rows += kv.second.n;
+    for (const auto& kv : R.delta_ord) rows += kv.second.n;
+    b += rows * R.arity * 4ull;
+  }
+  return b;
+}
+
 // Raw head rows of one chunk (canonical column order, unsorted unless
 // `presorted`: sorted, unique, above every row of the head's earlier chunks,
 // and from the head's only version).  `grouped`: the rows, all from one
@@ -1189,7 +1202,9 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     }
     size_t free_b = 0, total_b = 0;
     WCDL_HIP(hipMemGetInfo(&free_b, &total_b));
-    const u64 limit = e->cfg.mem_budget_bytes ? e->cfg.mem_budget_bytes / 4 : (u64)(total_b * 0.2);
+    // With a memory budget the arena shares what the relations leave of it.
+    const u64 held = resident_bytes(e), budget = e->cfg.mem_budget_bytes;
+    const u64 limit = budget ? (budget > held ? (budget - held) / 2 : 0) : (u64)(total_b * 0.2);
     const double scale = want_total > limit ? (double)limit / (double)want_total : 1.0;
     for (auto& kv : stage_plan) {
       const u64 per_chunk = STAGE_CHUNK * kv.first->v->plan.head_arity * 4ull;
@@ -1277,6 +1292,19 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     if (R.total == 0) R.skip = true;
   }
   st.phase[WCDL_PH_COUNT] += ms_since(t_count);
+  // Memory bound of the round: the counted rows must fit beside the
+  // relations within the budget, else nothing of this round is written.
+  if (e->cfg.mem_budget_bytes) {
+    u64 need = 0;
+    for (auto& R : runs)
+      if (!R.skip) need += R.total * R.v->plan.head_arity * 4ull;
+    const u64 held = resident_bytes(e);
+    if (held + need > e->cfg.mem_budget_bytes)
+      throw Error(WCDL_E_BUDGET, "the round's count pass found " + std::to_string(need) +
+                                     " bytes of rows beside " + std::to_string(held) +
+                                     " bytes of relations, beyond the budget of " +
+                                     std::to_string(e->cfg.mem_budget_bytes) + " bytes");
+  }
   // ---- Resize: one candidate buffer per head relation.  A head whose rows
   // exceed the chunk budget is materialized in ranges of workgroups (or of
   // units, for cross-product plans) instead, each range deduplicated by the
@@ -1292,8 +1320,7 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
   }
   size_t free_b = 0, total_b = 0;
   WCDL_HIP(hipMemGetInfo(&free_b, &total_b));
-  const u64 chunk_bytes = e->cfg.mem_budget_bytes ? e->cfg.mem_budget_bytes / 4
-                                                  : (u64)(total_b * 0.06);
+  const u64 chunk_bytes = e->cfg.chunk_bytes ? e->cfg.chunk_bytes : (u64)(total_b * 0.06);
   // A head written by one version whose rows come out sorted and unique,
   // into an empty relation, needs no scratch beyond its final size: it is
   // written whole unless that size itself is large against the memory.
@@ -1305,7 +1332,7 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
                 e->rels[R.v->head_rel].full.n == 0;
       in_order[R.v->head_rel] = it == in_order.end() ? ok : it->second && ok;
     }
-  const u64 direct_bytes = e->cfg.mem_budget_bytes ? e->cfg.mem_budget_bytes / 2 : (u64)(free_b / 2);
+  const u64 direct_bytes = free_b / 2;
   std::set<u32> chunked;
   for (auto& kv : rows) {
     const u64 bytes = kv.second * e->rels[kv.first].arity * 4ull;

@@ -50,7 +50,8 @@ class _Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("n_streams", ctypes.c_uint32),
                 ("streams", ctypes.POINTER(ctypes.c_void_p)), ("alloc", _Allocator),
                 ("mem_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("wg_per_cu", ctypes.c_uint32), ("stage_pct", ctypes.c_uint32)]
+                ("wg_per_cu", ctypes.c_uint32), ("stage_pct", ctypes.c_uint32),
+                ("chunk_bytes", ctypes.c_uint64)]
 
 
 class _Stats(ctypes.Structure):
@@ -159,7 +160,7 @@ class Engine:
 
     def __init__(self, device: int = 0, streams=None, flags: int = 0, mem_budget: int = 0,
                  wg_per_cu: int = 0, stage_pct: int = 0, torch_alloc: bool = True,
-                 batched: bool = False):
+                 batched: bool = False, chunk_bytes: int = 0):
         import torch  # device memory and streams come from PyTorch
 
         self._torch = torch
@@ -174,6 +175,7 @@ class Engine:
         cfg.mem_budget_bytes = mem_budget
         cfg.wg_per_cu = wg_per_cu
         cfg.stage_pct = stage_pct
+        cfg.chunk_bytes = chunk_bytes
         self._keep = []
         if torch_alloc:
             dev = torch.device("cuda", device)

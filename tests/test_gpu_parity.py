@@ -233,21 +233,21 @@ def test_errors_do_not_poison_the_engine():
 
 
 def test_chunked_materialization_nonrecursive():
-    """A memory budget smaller than the join output: rows are written and
+    """A chunk size smaller than the join output: rows are written and
     deduplicated in ranges of workgroups; the result is unchanged."""
     edges = W.complete_graph(60)
     check_parity({"edge": 2, "tri": 3, "path": 2}, TRI + "\n" + TC, {"edge": edges},
-                 mem_budget=4 * 12 * 20000)
+                 chunk_bytes=4 * 12 * 20000)
 
 
 def test_chunked_materialization_recursive():
     rel = W.andersen_scaled(W.SEED_BASE + 2, 0.004)
     names = {"addressOf": 2, "assign": 2, "load": 2, "store": 2, "pt": 2}
-    check_parity(names, ANDERSEN, rel, mem_budget=4 * 8 * 50000)
+    check_parity(names, ANDERSEN, rel, chunk_bytes=4 * 8 * 50000)
 
 
 def test_memory_budget_is_enforced():
-    """Even one work unit (one edge; 58 triangles) exceeds this budget."""
+    """The loaded edges alone exceed this budget: the first round fails."""
     edges = W.complete_graph(60)
     e = Engine(mem_budget=4 * 12 * 10)
     e.declare("edge", 2)
@@ -257,6 +257,41 @@ def test_memory_budget_is_enforced():
     with pytest.raises(WcdlError) as ei:
         e.run()
     assert ei.value.code == -8
+    e.close()
+
+
+def test_budget_failure_keeps_last_round_and_engine_usable():
+    """Transitive closure of a 3,000-node path under a budget that the
+    closure outgrows: the run fails with E_BUDGET in some round, the path
+    relation then holds exactly the pairs of the rounds completed before it
+    (pairs at distance <= j for some j, the oracle's state after round j),
+    and the same engine then runs a smaller input to the oracle's result."""
+    n = 3000
+    edges = W.path_graph(n)
+    o, full = oracle.evaluate({"edge": 2, "path": 2}, TC, {"edge": edges})
+    deltas = o.delta_sizes("path")  # delta_k: the pairs at distance k + 1
+    budget = 24 << 20                # far below |path| = 4.5M rows x 8 bytes x copies
+    e = Engine(mem_budget=budget)
+    e.declare("edge", 2)
+    e.declare("path", 2)
+    e.add_rules(TC)
+    e.load("edge", edges)
+    with pytest.raises(WcdlError) as ei:
+        e.run()
+    assert ei.value.code == -8
+    got = e.read_numpy("path")
+    sizes = list(np.cumsum(deltas))
+    assert len(got) in sizes and 0 < len(got) < len(full["path"])
+    j = sizes.index(len(got)) + 1    # distances 1..j are complete
+    assert j > 1
+    assert np.all(got[:, 1] > got[:, 0]) and np.all(got[:, 1] - got[:, 0] <= j)
+    assert np.array_equal(got, full["path"][full["path"][:, 1] - full["path"][:, 0] <= j])
+    small = W.er_graph(300, 900, 51)
+    e.clear("edge")
+    e.load("edge", small)
+    e.run()
+    _, expect = oracle.evaluate({"edge": 2, "path": 2}, TC, {"edge": small})
+    assert np.array_equal(e.read_numpy("path"), expect["path"])
     e.close()
 
 
