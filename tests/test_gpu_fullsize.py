@@ -3,7 +3,7 @@ workload's own size (GPU required).
 
 The workload is an R-MAT graph on 2^20 nodes with 2^24 distinct edges and
 the triangle and 4-clique rules (4-cliques of the ascending-edge DAG), run
-exactly as the benchmark runs it: q split twice into the shared
+exactly as the benchmark runs it: q split three times into the shared
 ascending-triangle helper (Sec. 5).  Its 4-clique relation has more than
 2^31 rows, so row offsets, staging chunk tags and the write pass take their
 64-bit paths here and nowhere else.
@@ -46,6 +46,7 @@ def engine_tri_q(edges, split=True, **kw):
     if split:
         e.split_rule(1, [0, 1, 2])
         e.split_rule(1, [0, 4, 5])
+        e.split_rule(1, [2, 3, 5])
     e.load("edge", edges)
     e.run()
     return e

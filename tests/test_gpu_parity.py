@@ -542,6 +542,32 @@ def test_split_q_overlapping_helpers_reused():
     e.close()
 
 
+def test_split_q_three_triangle_helpers():
+    """A third split of q over {edge(w,y), edge(y,z), edge(w,z)} (one atom
+    still in the body, two already inside the helper) is the ascending
+    triangles again: q(w,x,y,z) :- T(w,x,y), T(w,x,z), T(w,y,z), y < z, the
+    form the benchmark runs.  q unchanged, no new helper."""
+    edges = W.rmat_graph(12, 40000, 57)
+    rules = TRI + "\n" + Q4
+    _, expect = oracle.evaluate({"edge": 2, "tri": 3, "q": 4}, rules, {"edge": edges})
+    e = Engine()
+    for n, k in {"edge": 2, "tri": 3, "q": 4}.items():
+        e.declare(n, k)
+    e.add_rules(rules)
+    h1 = e.split_rule(1, [0, 1, 2])
+    n_rules = e.rule_count()
+    assert e.split_rule(1, [0, 4, 5]) == h1
+    assert e.split_rule(1, [2, 3, 5]) == h1 and e.rule_count() == n_rules
+    with pytest.raises(WcdlError):
+        e.split_rule(1, [3])  # every atom of the body as registered is now in a helper
+    e.load("edge", edges)
+    e.run()
+    assert np.array_equal(e.read_numpy("q"), expect["q"])
+    assert np.array_equal(e.read_numpy("tri"), expect["tri"])
+    assert len(expect["q"]) > 1000
+    e.close()
+
+
 SG = ("sg(x,y) :- par(p,x), par(p,y), x != y.\n"
       "sg(x,y) :- par(a,x), sg(a,b), par(b,y).")
 
@@ -613,6 +639,43 @@ def test_hub_runs_bitmaps(flags):
         assert np.array_equal(e.read_numpy("tri"), expect["tri"])
         assert np.array_equal(e.read_numpy("q"), expect["q"])
     assert len(expect["q"]) > 0
+    e.close()
+
+
+@pytest.mark.parametrize("flags", [0, WCDL_F_RUN_BITMAPS_OFF])
+def test_run_bitmaps_mixed_lengths_and_extreme_values(flags):
+    """Adjacency runs of lengths around the bitmap threshold (63, 64, 65,
+    300, 511, 512, 4,000 rows), the value 2^32 - 1 in the last column (the
+    bitmaps then span the whole 32-bit range), and 4-cycles whose closing
+    atom reads the reverse order of the same relation; results equal the
+    oracle's."""
+    rng = np.random.default_rng(321)
+    big = np.uint32(0xFFFFFFFF)
+    rows = []
+    for h, d in enumerate([63, 64, 65, 300, 511, 512, 4000]):
+        nb = rng.choice(np.arange(20, 9000, dtype=np.uint32), d, replace=False)
+        rows.append(np.stack([np.full(d, h, np.uint32), nb], axis=1))
+        rows.append(np.array([[h, big], [big, h]], np.uint32))
+    rows.append(rng.integers(0, 9000, size=(30000, 2)).astype(np.uint32))
+    rows.append(rng.integers(0, 400, size=(12000, 2)).astype(np.uint32))  # dense core
+    rows.append(np.stack([rng.integers(0, 9000, 200).astype(np.uint32),
+                          np.full(200, big, np.uint32)], axis=1))
+    edges = np.unique(np.concatenate(rows), axis=0)
+    edges = edges[edges[:, 0] != edges[:, 1]]
+    rels = {"edge": 2, "tri": 3, "q": 4, "e": 2, "c": 4}
+    rules = TRI + "\n" + Q4 + "\n" + C4
+    facts = {"edge": edges, "e": edges[edges[:, 0] < 300]}
+    _, expect = oracle.evaluate(rels, rules, facts)
+    e = Engine(flags=flags)
+    for nm, k in rels.items():
+        e.declare(nm, k)
+    e.add_rules(rules)
+    for nm, r in facts.items():
+        e.load(nm, r)
+    e.run()
+    for nm in ("tri", "q", "c"):
+        assert np.array_equal(e.read_numpy(nm), expect[nm]), nm
+    assert len(expect["tri"]) > 0 and len(expect["q"]) > 0
     e.close()
 
 

@@ -444,6 +444,11 @@ def test_4clique_through_shared_triangle_helper_same_model(seed):
     _, split = oracle.evaluate({"edge": 2, "T": 3, "q": 4}, rewritten, {"edge": edges})
     _, plain = oracle.evaluate({"edge": 2, "q": 4}, Q4, {"edge": edges})
     assert np.array_equal(split["q"], plain["q"])
+    # Third split: the closing edge(y,z) with edge(w,y), edge(w,z) is T(w,y,z).
+    all_t = ("T(a,b,c) :- edge(a,b), edge(b,c), edge(a,c), a < b, b < c, a < c.\n"
+             "q(w,x,y,z) :- T(w,x,y), T(w,x,z), T(w,y,z), w < x, x < y, y < z.")
+    _, split3 = oracle.evaluate({"edge": 2, "T": 3, "q": 4}, all_t, {"edge": edges})
+    assert np.array_equal(split3["q"], plain["q"])
     es = {tuple(r) for r in edges.tolist()}
     nodes = sorted({v for r in es for v in r})
     adj = {v: set() for v in nodes}
