@@ -52,6 +52,8 @@ typedef int32_t wcdl_status;
 #define WCDL_E_BUDGET (-8)        /* a count-pass bound exceeded mem_budget_bytes */
 #define WCDL_E_DEVICE (-9)        /* HIP runtime error; the engine must be destroyed */
 #define WCDL_E_PARSE (-10)        /* rule text does not parse */
+#define WCDL_E_CHECK (-11)        /* checked mode (WCDL_F_CHECKED): a relation
+                                     invariant failed; the engine must be destroyed */
 
 /* Static limits of one rule (after the planner's rewrites). */
 #define WCDL_MAX_ARITY 6
@@ -84,6 +86,13 @@ typedef int32_t wcdl_status;
                                     of all but its last column (Sec. 4, Compute
                                     Delta: the grouped sort orders and dedups
                                     such chunks one LDS tile of groups at a time) */
+#define WCDL_F_CHECKED 0x200u    /* checked mode: after every merge the engine
+                                    verifies on the device that each stored copy
+                                    of the relation is sorted without repeats and
+                                    that the delta held no row the relation
+                                    already had (Sec. 2: deltas are the new facts
+                                    of a round); a failure is WCDL_E_CHECK.
+                                    Costs one pass over the relation per merge. */
 #define WCDL_F_BATCHED 0x10u     /* batched mode: the engine holds many independent
                                     instances of one program.  Every relation gets
                                     an implicit leading column, the instance id:
@@ -372,6 +381,59 @@ wcdl_status wcdl_serve_release(wcdl_engine* e, const uint32_t* ids, uint64_t n);
 
 /* Stop serving (relations keep their contents). */
 wcdl_status wcdl_serve_end(wcdl_engine* e);
+
+/* ---- Instances (batched engines) --------------------------------------
+ *
+ * An engine created with WCDL_F_BATCHED holds one compiled program; an
+ * instance is one set of input facts of it, with its own least model.  Each
+ * instance's rows carry its id in the leading column of every relation, so
+ * many instances run in the same launches of every phase and never mix (the
+ * instance variable occurs in every atom of every rule). */
+
+typedef struct wcdl_instance wcdl_instance;
+
+/* A new, empty instance; ids are handed out from 0 up. */
+wcdl_status wcdl_instance_create(wcdl_engine* e, wcdl_instance** out);
+
+/* The instance's id (the value of its leading column); 0xffffffff for NULL. */
+uint32_t wcdl_instance_id(const wcdl_instance* in);
+
+/* Add facts to the instance: cols[j] (j < declared arity) points to n_rows
+ * values of column j, host or device memory as on_device says (the engine
+ * copies them and prepends the instance column).  Outside serving they join
+ * the loaded facts (wcdl_load_columns); while serving they are admitted for
+ * the next step (wcdl_serve_admit). */
+wcdl_status wcdl_instance_load(wcdl_instance* in, uint32_t rel, const uint32_t* const* cols,
+                               uint64_t n_rows, int on_device);
+
+/* Rows the relation holds for this instance. */
+wcdl_status wcdl_instance_size(const wcdl_instance* in, uint32_t rel, uint64_t* n_rows);
+
+/* Copy this instance's rows of a relation out, sorted and deduplicated,
+ * without the instance column: cols_out[j] (j < declared arity) receives
+ * min(size, capacity) values. */
+wcdl_status wcdl_instance_read(const wcdl_instance* in, uint32_t rel, uint32_t* const* cols_out,
+                               uint64_t capacity, uint64_t* n_written, int on_device);
+
+/* Drop every row of the instance from every relation and free the handle. */
+void wcdl_instance_destroy(wcdl_instance* in);
+
+/* Evaluate the program for the listed instances together (one run: every
+ * phase of every round covers all of them at once).  Afterwards the derived
+ * relations hold exactly these instances' least models (rows of other
+ * instances are not derived; their loaded facts stay).  Not while serving. */
+wcdl_status wcdl_run_batch(wcdl_engine* e, wcdl_instance* const* v, uint32_t n,
+                           wcdl_run_stats* stats);
+
+/* While serving: one semi-naive round for the listed instances (admitted
+ * facts of theirs not yet known join the round's deltas first); the work of
+ * every other instance waits for a later step.  done[i] (if not NULL)
+ * receives 1 when active[i] has reached its fixpoint (no delta rows and no
+ * admitted facts left).  *next_bound_bytes (if not NULL) receives the bytes
+ * the relations hold after the step plus the bytes this step's count passes
+ * counted: the memory bound of the next step for admission decisions. */
+wcdl_status wcdl_step(wcdl_engine* e, wcdl_instance* const* active, uint32_t n, uint8_t* done,
+                      uint64_t* next_bound_bytes);
 
 /* Sizes of a relation's per-round deltas in its (recursive) stratum during
  * the last run: |delta_0|, |delta_1|, ..., ending with the empty one.

@@ -245,6 +245,15 @@ struct wcdl_engine {
   bool serving = false;
   std::vector<wcdl::Version> serve_versions;
   std::map<uint32_t, wcdl::Cols> pending;
+  // Instances (batched engines): ids handed out so far.
+  uint32_t next_instance = 0;
+};
+
+// An instance of a batched engine's program: its rows carry `id` in the
+// leading column of every relation.
+struct wcdl_instance {
+  wcdl_engine* e = nullptr;
+  uint32_t id = 0;
 };
 
 namespace wcdl {
@@ -856,6 +865,7 @@ struct Stats {
   u64 launches[4] = {0};
   u64 examined = 0;
   u64 exam_level[MAXV] = {0};
+  u64 bound_bytes = 0;  // bytes of candidate rows counted by count passes
 };
 
 // HIP events around one kernel launch on its stream; read after a sync.
@@ -1294,10 +1304,11 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
   st.phase[WCDL_PH_COUNT] += ms_since(t_count);
   // Memory bound of the round: the counted rows must fit beside the
   // relations within the budget, else nothing of this round is written.
+  u64 need = 0;
+  for (auto& R : runs)
+    if (!R.skip) need += R.total * R.v->plan.head_arity * 4ull;
+  st.bound_bytes += need;
   if (e->cfg.mem_budget_bytes) {
-    u64 need = 0;
-    for (auto& R : runs)
-      if (!R.skip) need += R.total * R.v->plan.head_arity * 4ull;
     const u64 held = resident_bytes(e);
     if (held + need > e->cfg.mem_budget_bytes)
       throw Error(WCDL_E_BUDGET, "the round's count pass found " + std::to_string(need) +
@@ -1615,14 +1626,50 @@ constexpr u64 HEAD_MIN_ROWS = 1u << 16;
 // other column orders) only past a share of the body's size, so a long tail
 // of small deltas does not rewrite the body every round; otherwise straight
 // into full and every other maintained column order of it.
+// Checked mode (WCDL_F_CHECKED): relation invariants, verified on the device.
+bool checked(const Engine* e) { return (e->cfg.flags & WCDL_F_CHECKED) != 0; }
+
+void check_sorted(Engine* e, const Cols& c, const char* what, u32 rel) {
+  if (c.n < 2) return;
+  auto p = c.ptrs();
+  const u64 bad = order_violations(ctx(e), c.arity(), p.data(), c.n);
+  if (bad)
+    throw Error(WCDL_E_CHECK, std::string(what) + " of relation " + e->rels[rel].name + " has " +
+                                  std::to_string(bad) + " rows out of order or repeated");
+}
+
+// A delta about to be merged: sorted, unique, and disjoint from the relation.
+void check_delta(Engine* e, u32 rel, const Cols& d) {
+  Relation& R = e->rels[rel];
+  check_sorted(e, d, "a delta", rel);
+  if (d.n && (R.full.n || R.head.n)) {
+    auto dp = d.ptrs(), fp = R.full.ptrs();
+    std::vector<const u32*> hp;
+    if (R.head.n) hp = R.head.ptrs();
+    DBuf<u32> tmp[MAXA];
+    std::vector<u32*> op;
+    for (u32 j = 0; j < d.arity(); ++j) {
+      tmp[j] = DBuf<u32>(e->mem.get(), d.n);
+      op.push_back(tmp[j].get());
+    }
+    const u64 kept = set_difference(ctx(e), d.arity(), dp.data(), d.n, fp.data(), R.full.n,
+                                    op.data(), hp.empty() ? nullptr : hp.data(), R.head.n);
+    if (kept != d.n)
+      throw Error(WCDL_E_CHECK, "a delta of relation " + R.name + " repeats " +
+                                    std::to_string(d.n - kept) + " rows it already holds");
+  }
+}
+
 void commit_delta(Engine* e, u32 rel, Cols& d, Stats& st, bool consume = false,
                   bool use_head = false) {
   Relation& R = e->rels[rel];
+  if (checked(e)) check_delta(e, rel, d);
   auto t = Clock::now();
   if (d.n && use_head && R.full.n) {
     R.head = R.head.n == 0 ? copy_cols(e, d) : merged(e, 0, R.head, d);
     WCDL_HIP(hipStreamSynchronize(e->streams[0]));
     st.phase[WCDL_PH_MERGE] += ms_since(t);
+    if (checked(e)) check_sorted(e, R.head, "the head run", rel);
     if (R.head.n > std::max<u64>(HEAD_MIN_ROWS, R.full.n / HEAD_RATIO)) flush_head(e, rel, &st);
     return;
   }
@@ -1640,6 +1687,10 @@ void commit_delta(Engine* e, u32 rel, Cols& d, Stats& st, bool consume = false,
   }
   WCDL_HIP(hipStreamSynchronize(e->streams[0]));
   st.phase[WCDL_PH_MERGE] += ms_since(t);
+  if (checked(e)) {
+    check_sorted(e, R.full, "the relation", rel);
+    for (auto& kv : R.full_ord) check_sorted(e, kv.second, "a column order", rel);
+  }
 }
 
 // Evaluate versions and return the rows new to each head relation.
@@ -1654,11 +1705,43 @@ std::map<u32, Cols> new_rows(Engine* e, std::vector<Version>& vs, Stats& st) {
   return acc;
 }
 
-void run_program(Engine* e, wcdl_run_stats* stats_out) {
+// Rows of `c` whose leading (instance) column is (keep) or is not (!keep) in
+// the sorted id list.
+Cols select_instances(Engine* e, const Cols& c, const DBuf<u32>& ids, u64 nids, bool keep) {
+  Cols out;
+  out.order = c.order;
+  const u32 k = c.arity();
+  if (c.n == 0) {
+    for (u32 j = 0; j < k; ++j) out.col.emplace_back();
+    return out;
+  }
+  const u32 pos0 = (u32)(std::find(c.order.begin(), c.order.end(), 0u) - c.order.begin());
+  std::vector<u32*> op;
+  for (u32 j = 0; j < k; ++j) {
+    out.col.emplace_back(e->mem.get(), c.n);
+    op.push_back(out.col.back().get());
+  }
+  auto ip = c.ptrs();
+  out.n = select_leading(ctx(e), k, ip.data(), c.n, pos0, ids.get(), nids, keep, op.data());
+  return out;
+}
+
+// Evaluate the program (Sec. 2 stratification, Sec. 4 loop).  `only`
+// (batched engines): start from the loaded facts of these instances alone.
+void run_program(Engine* e, wcdl_run_stats* stats_out, const std::vector<u32>* only = nullptr) {
   auto t0 = Clock::now();
   Stats st;
+  DBuf<u32> d_only;
+  if (only && !only->empty()) {
+    d_only = DBuf<u32>(e->mem.get(), only->size());
+    WCDL_HIP(hipMemcpy(d_only.get(), only->data(), only->size() * sizeof(u32), hipMemcpyHostToDevice));
+  }
   for (auto& R : e->rels) {
-    R.full = copy_cols(e, R.base);
+    if (only)
+      R.full = only->empty() ? empty_cols(R.arity, canonical(R.arity))
+                             : select_instances(e, R.base, d_only, only->size(), true);
+    else
+      R.full = copy_cols(e, R.base);
     R.head = empty_cols(R.arity, canonical(R.arity));
     R.full_ord.clear();
     R.delta_ord.clear();
@@ -2041,6 +2124,118 @@ std::string helper_key(const Rule& h) {
   std::sort(cs.begin(), cs.end());
   for (auto& c : cs) k += ";" + c;
   return k;
+}
+
+// One serving round: admitted facts not yet known join the deltas of their
+// relations, then one semi-naive round of every rule version over them.
+void serve_round(Engine* e, Stats& st, wcdl_step_stats& s) {
+  for (auto& kv : e->pending) {
+    Relation& R = e->rels[kv.first];
+    Cols d = difference(e, 0, kv.second, R.full);
+    const std::vector<u32> canon = canonical(R.arity);
+    Cols cur = empty_cols(R.arity, canon);
+    auto it = R.delta_ord.find(canon);
+    if (it != R.delta_ord.end()) cur = std::move(it->second);
+    commit_delta(e, kv.first, d, st);
+    Cols next = cur.n == 0 ? std::move(d) : (d.n ? merged(e, 0, cur, d) : std::move(cur));
+    R.delta_ord.clear();
+    R.delta_ord.emplace(canon, std::move(next));
+  }
+  e->pending.clear();
+  sync_all(e);
+  bool any = false;
+  for (auto& R : e->rels) {
+    auto it = R.delta_ord.find(canonical(R.arity));
+    if (it != R.delta_ord.end() && it->second.n) any = true;
+  }
+  if (any) {
+    auto fresh = new_rows(e, e->serve_versions, st);
+    for (u32 rel = 0; rel < e->rels.size(); ++rel) {
+      Relation& R = e->rels[rel];
+      auto it = fresh.find(rel);
+      Cols d = it != fresh.end() ? std::move(it->second) : empty_cols(R.arity, canonical(R.arity));
+      commit_delta(e, rel, d, st);
+      s.new_rows += d.n;
+      R.delta_ord.clear();
+      R.delta_ord.emplace(canonical(R.arity), std::move(d));
+    }
+    sync_all(e);
+  }
+  for (auto& R : e->rels) s.resident_rows += R.full.n;
+  s.candidate_rows = st.candidates;
+}
+
+// Instance ids that still have work: rows in some delta or pending facts.
+std::set<u32> live_instances(Engine* e) {
+  std::set<u32> live;
+  auto collect = [&](const Cols& c) {
+    if (c.n == 0) return;
+    const u32 pos0 = (u32)(std::find(c.order.begin(), c.order.end(), 0u) - c.order.begin());
+    DBuf<u32> out(e->mem.get(), c.n);
+    const u32* in = c.col[pos0].get();
+    u32* op = out.get();
+    // Distinct instance ids of a copy sorted with the instance column first.
+    u64 nd = unique_rows(ctx(e), 1, &in, c.n, &op);
+    std::vector<u32> h(nd);
+    WCDL_HIP(hipMemcpy(h.data(), out.get(), nd * sizeof(u32), hipMemcpyDeviceToHost));
+    live.insert(h.begin(), h.end());
+  };
+  for (auto& R : e->rels)
+    for (auto& kv : R.delta_ord)
+      if (!kv.first.empty() && kv.first[0] == 0) { collect(kv.second); break; }
+  for (auto& kv : e->pending) collect(kv.second);
+  return live;
+}
+
+// Sorted, deduplicated instance ids of handles that belong to `e`.
+std::vector<u32> instance_ids(Engine* e, wcdl_instance* const* v, u32 n) {
+  if (n && !v) throw Error(WCDL_E_INVALID, "null instance list");
+  std::vector<u32> ids;
+  for (u32 i = 0; i < n; ++i) {
+    if (!v[i] || v[i]->e != e) throw Error(WCDL_E_INVALID, "instance of another engine");
+    ids.push_back(v[i]->id);
+  }
+  std::sort(ids.begin(), ids.end());
+  ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+  return ids;
+}
+
+// Drop every row of the listed instances (sorted ids) from every relation.
+void drop_instances(Engine* e, const std::vector<u32>& ids) {
+  if (ids.empty()) return;
+  DBuf<u32> d_ids(e->mem.get(), ids.size());
+  WCDL_HIP(hipMemcpy(d_ids.get(), ids.data(), ids.size() * sizeof(u32), hipMemcpyHostToDevice));
+  auto drop = [&](Cols& c) {
+    if (c.n) c = select_instances(e, c, d_ids, ids.size(), false);
+  };
+  for (auto& R : e->rels) {
+    if (R.head.n) flush_head(e, (u32)(&R - e->rels.data()), nullptr);
+    drop(R.full);
+    drop(R.base);
+    for (auto& kv : R.full_ord) drop(kv.second);
+    for (auto& kv : R.delta_ord) drop(kv.second);
+  }
+  for (auto& kv : e->pending) drop(kv.second);
+  sync_all(e);
+}
+
+// Device columns of an instance's rows: the instance id column, then the
+// caller's columns (host or device).
+std::vector<DBuf<u32>> instance_columns(Engine* e, u32 rel, u32 id, const u32* const* cols, u64 n,
+                                        int on_device) {
+  const u32 k = e->rels[rel].arity;
+  if (!cols) throw Error(WCDL_E_INVALID, "null columns");
+  std::vector<DBuf<u32>> tmp;
+  tmp.emplace_back(e->mem.get(), n);
+  fill_u32(ctx(e), tmp.back().get(), n, id);
+  for (u32 j = 1; j < k; ++j) {
+    if (!cols[j - 1]) throw Error(WCDL_E_INVALID, "null column pointer");
+    tmp.emplace_back(e->mem.get(), n);
+    WCDL_HIP(hipMemcpyAsync(tmp.back().get(), cols[j - 1], n * sizeof(u32),
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            e->streams[0]));
+  }
+  return tmp;
 }
 
 }  // namespace wcdl
@@ -2492,42 +2687,8 @@ wcdl_status wcdl_serve_step(wcdl_engine* e, wcdl_step_stats* out) {
     if (!e->serving) throw Error(WCDL_E_STATE, "not serving");
     auto t0 = Clock::now();
     Stats st;
-    // Admitted facts not yet known join this round's deltas.
-    for (auto& kv : e->pending) {
-      Relation& R = e->rels[kv.first];
-      Cols d = difference(e, 0, kv.second, R.full);
-      const std::vector<u32> canon = canonical(R.arity);
-      Cols cur = empty_cols(R.arity, canon);
-      auto it = R.delta_ord.find(canon);
-      if (it != R.delta_ord.end()) cur = std::move(it->second);
-      commit_delta(e, kv.first, d, st);
-      Cols next = cur.n == 0 ? std::move(d) : (d.n ? merged(e, 0, cur, d) : std::move(cur));
-      R.delta_ord.clear();
-      R.delta_ord.emplace(canon, std::move(next));
-    }
-    e->pending.clear();
-    sync_all(e);
-    bool any = false;
-    for (auto& R : e->rels) {
-      auto it = R.delta_ord.find(canonical(R.arity));
-      if (it != R.delta_ord.end() && it->second.n) any = true;
-    }
     wcdl_step_stats s{};
-    if (any) {
-      auto fresh = new_rows(e, e->serve_versions, st);
-      for (u32 rel = 0; rel < e->rels.size(); ++rel) {
-        Relation& R = e->rels[rel];
-        auto it = fresh.find(rel);
-        Cols d = it != fresh.end() ? std::move(it->second) : empty_cols(R.arity, canonical(R.arity));
-        commit_delta(e, rel, d, st);
-        s.new_rows += d.n;
-        R.delta_ord.clear();
-        R.delta_ord.emplace(canonical(R.arity), std::move(d));
-      }
-      sync_all(e);
-    }
-    for (auto& R : e->rels) s.resident_rows += R.full.n;
-    s.candidate_rows = st.candidates;
+    serve_round(e, st, s);
     s.wall_ms = ms_since(t0);
     if (out) *out = s;
   });
@@ -2536,23 +2697,7 @@ wcdl_status wcdl_serve_step(wcdl_engine* e, wcdl_step_stats* out) {
 wcdl_status wcdl_serve_live(wcdl_engine* e, uint32_t* ids, uint64_t cap, uint64_t* count) {
   return guarded(e, [&] {
     if (!e->serving) throw Error(WCDL_E_STATE, "not serving");
-    std::set<u32> live;
-    auto collect = [&](const Cols& c) {
-      if (c.n == 0) return;
-      const u32 pos0 = (u32)(std::find(c.order.begin(), c.order.end(), 0u) - c.order.begin());
-      DBuf<u32> out(e->mem.get(), c.n);
-      const u32* in = c.col[pos0].get();
-      u32* op = out.get();
-      // Distinct instance ids of a copy sorted with the instance column first.
-      u64 nd = unique_rows(ctx(e), 1, &in, c.n, &op);
-      std::vector<u32> h(nd);
-      WCDL_HIP(hipMemcpy(h.data(), out.get(), nd * sizeof(u32), hipMemcpyDeviceToHost));
-      live.insert(h.begin(), h.end());
-    };
-    for (auto& R : e->rels)
-      for (auto& kv : R.delta_ord)
-        if (!kv.first.empty() && kv.first[0] == 0) { collect(kv.second); break; }
-    for (auto& kv : e->pending) collect(kv.second);
+    const std::set<u32> live = live_instances(e);
     u64 i = 0;
     for (u32 v : live) {
       if (ids && i < cap) ids[i] = v;
@@ -2570,31 +2715,7 @@ wcdl_status wcdl_serve_release(wcdl_engine* e, const uint32_t* ids, uint64_t n) 
     std::vector<u32> h(ids, ids + n);
     std::sort(h.begin(), h.end());
     h.erase(std::unique(h.begin(), h.end()), h.end());
-    DBuf<u32> d_ids(e->mem.get(), h.size());
-    WCDL_HIP(hipMemcpy(d_ids.get(), h.data(), h.size() * sizeof(u32), hipMemcpyHostToDevice));
-    auto drop = [&](Cols& c) {
-      if (c.n == 0) return;
-      const u32 k = c.arity();
-      const u32 pos0 = (u32)(std::find(c.order.begin(), c.order.end(), 0u) - c.order.begin());
-      Cols out;
-      out.order = c.order;
-      std::vector<u32*> op;
-      for (u32 j = 0; j < k; ++j) {
-        out.col.emplace_back(e->mem.get(), c.n);
-        op.push_back(out.col.back().get());
-      }
-      auto ip = c.ptrs();
-      out.n = drop_leading(ctx(e), k, ip.data(), c.n, pos0, d_ids.get(), h.size(), op.data());
-      c = std::move(out);
-    };
-    for (auto& R : e->rels) {
-      drop(R.full);
-      drop(R.base);
-      for (auto& kv : R.full_ord) drop(kv.second);
-      for (auto& kv : R.delta_ord) drop(kv.second);
-    }
-    for (auto& kv : e->pending) drop(kv.second);
-    sync_all(e);
+    drop_instances(e, h);
   });
 }
 
@@ -2603,6 +2724,154 @@ wcdl_status wcdl_serve_end(wcdl_engine* e) {
     e->serving = false;
     e->serve_versions.clear();
     e->pending.clear();
+  });
+}
+
+wcdl_status wcdl_instance_create(wcdl_engine* e, wcdl_instance** out) {
+  return guarded(e, [&] {
+    if (!out) throw Error(WCDL_E_INVALID, "null output");
+    *out = nullptr;
+    if (!batched(e)) throw Error(WCDL_E_STATE, "instances need a batched engine");
+    if (e->next_instance == NONE) throw Error(WCDL_E_UNSUPPORTED, "instance ids exhausted");
+    auto* in = new wcdl_instance();
+    in->e = e;
+    in->id = e->next_instance++;
+    *out = in;
+  });
+}
+
+uint32_t wcdl_instance_id(const wcdl_instance* in) { return in ? in->id : NONE; }
+
+wcdl_status wcdl_instance_load(wcdl_instance* in, uint32_t rel, const uint32_t* const* cols,
+                               uint64_t n_rows, int on_device) {
+  if (!in) return WCDL_E_INVALID;
+  wcdl_engine* e = in->e;
+  return guarded(e, [&] {
+    if (rel >= e->rels.size()) throw Error(WCDL_E_UNKNOWN_REL, "unknown relation id");
+    if (n_rows == 0) return;
+    auto tmp = instance_columns(e, rel, in->id, cols, n_rows, on_device);
+    std::vector<const u32*> dp;
+    for (auto& t : tmp) dp.push_back(t.get());
+    const u32 k = e->rels[rel].arity;
+    if (!e->serving) {
+      add_facts(e, rel, dp, n_rows);
+      return;
+    }
+    Cols srt = sort_rows(e, 0, canonical(k), dp, n_rows, true);
+    auto it = e->pending.find(rel);
+    if (it == e->pending.end()) {
+      e->pending.emplace(rel, std::move(srt));
+    } else {
+      Cols d = difference(e, 0, srt, it->second);
+      if (d.n) it->second = merged(e, 0, it->second, d);
+    }
+    sync_all(e);
+  });
+}
+
+wcdl_status wcdl_instance_size(const wcdl_instance* in, uint32_t rel, uint64_t* n_rows) {
+  if (!in) return WCDL_E_INVALID;
+  uint64_t first = 0;
+  return wcdl_relation_range(in->e, rel, in->id, &first, n_rows);
+}
+
+wcdl_status wcdl_instance_read(const wcdl_instance* in, uint32_t rel, uint32_t* const* cols_out,
+                               uint64_t capacity, uint64_t* n_written, int on_device) {
+  if (!in) return WCDL_E_INVALID;
+  wcdl_engine* e = in->e;
+  uint64_t first = 0, count = 0;
+  wcdl_status rc = wcdl_relation_range(e, rel, in->id, &first, &count);
+  if (rc != WCDL_OK) return rc;
+  return guarded(e, [&] {
+    const Relation& R = e->rels[rel];
+    const Cols& src = R.full.n ? R.full : R.base;
+    const u64 n = std::min<u64>(count, capacity);
+    if (n && !cols_out) throw Error(WCDL_E_INVALID, "null output columns");
+    for (u32 j = 1; j < R.arity && n; ++j) {
+      if (!cols_out[j - 1]) throw Error(WCDL_E_INVALID, "null output column");
+      WCDL_HIP(hipMemcpyAsync(cols_out[j - 1], src.col[j].get() + first, n * sizeof(u32),
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                              e->streams[0]));
+    }
+    WCDL_HIP(hipStreamSynchronize(e->streams[0]));
+    if (n_written) *n_written = n;
+  });
+}
+
+void wcdl_instance_destroy(wcdl_instance* in) {
+  if (!in) return;
+  wcdl_engine* e = in->e;
+  const std::vector<u32> ids{in->id};
+  (void)guarded(e, [&] { drop_instances(e, ids); });
+  delete in;
+}
+
+wcdl_status wcdl_run_batch(wcdl_engine* e, wcdl_instance* const* v, uint32_t n,
+                           wcdl_run_stats* stats) {
+  return guarded(e, [&] {
+    if (!batched(e)) throw Error(WCDL_E_STATE, "wcdl_run_batch needs a batched engine");
+    if (e->serving) throw Error(WCDL_E_STATE, "the engine is serving");
+    const std::vector<u32> ids = instance_ids(e, v, n);
+    run_program(e, stats, &ids);
+  });
+}
+
+wcdl_status wcdl_step(wcdl_engine* e, wcdl_instance* const* active, uint32_t n, uint8_t* done,
+                      uint64_t* next_bound_bytes) {
+  return guarded(e, [&] {
+    if (!e->serving) throw Error(WCDL_E_STATE, "not serving (wcdl_serve_begin first)");
+    const std::vector<u32> ids = instance_ids(e, active, n);
+    DBuf<u32> d_ids;
+    if (!ids.empty()) {
+      d_ids = DBuf<u32>(e->mem.get(), ids.size());
+      WCDL_HIP(hipMemcpy(d_ids.get(), ids.data(), ids.size() * sizeof(u32), hipMemcpyHostToDevice));
+    }
+    // Work of instances outside the active set waits: their delta rows and
+    // admitted facts are set aside for this round and put back after it.
+    std::map<u32, Cols> held_delta, held_pending;
+    for (u32 rel = 0; rel < e->rels.size(); ++rel) {
+      Relation& R = e->rels[rel];
+      const std::vector<u32> canon = canonical(R.arity);
+      auto it = R.delta_ord.find(canon);
+      if (it != R.delta_ord.end() && it->second.n) {
+        Cols cur = std::move(it->second);
+        R.delta_ord.clear();
+        if (ids.empty()) {
+          held_delta.emplace(rel, std::move(cur));
+          R.delta_ord.emplace(canon, empty_cols(R.arity, canon));
+        } else {
+          held_delta.emplace(rel, select_instances(e, cur, d_ids, ids.size(), false));
+          R.delta_ord.emplace(canon, select_instances(e, cur, d_ids, ids.size(), true));
+        }
+      }
+    }
+    for (auto& kv : e->pending) {
+      Cols rest = ids.empty() ? std::move(kv.second)
+                              : select_instances(e, kv.second, d_ids, ids.size(), false);
+      if (!ids.empty()) kv.second = select_instances(e, kv.second, d_ids, ids.size(), true);
+      else kv.second = empty_cols(rest.arity(), rest.order);
+      if (rest.n) held_pending.emplace(kv.first, std::move(rest));
+    }
+    sync_all(e);
+    Stats st;
+    wcdl_step_stats s{};
+    serve_round(e, st, s);
+    for (auto& kv : held_delta) {
+      if (kv.second.n == 0) continue;
+      Relation& R = e->rels[kv.first];
+      const std::vector<u32> canon = canonical(R.arity);
+      auto it = R.delta_ord.find(canon);
+      Cols cur = it != R.delta_ord.end() ? std::move(it->second) : empty_cols(R.arity, canon);
+      R.delta_ord.clear();
+      R.delta_ord.emplace(canon, cur.n ? merged(e, 0, cur, kv.second) : std::move(kv.second));
+    }
+    for (auto& kv : held_pending) e->pending.emplace(kv.first, std::move(kv.second));
+    sync_all(e);
+    if (done) {
+      const std::set<u32> live = live_instances(e);
+      for (u32 i = 0; i < n; ++i) done[i] = live.count(active[i]->id) ? 0 : 1;
+    }
+    if (next_bound_bytes) *next_bound_bytes = resident_bytes(e) + st.bound_bytes;
   });
 }
 

@@ -650,7 +650,7 @@ __global__ __launch_bounds__(WG) void k_merge_tile(ColsIn a, ColsIn b, ColsOut o
 }
 
 __global__ __launch_bounds__(WG) void k_keep_flags(const u32* lead, u64 n, const u32* ids,
-                                                   u64 nids, u32* flags) {
+                                                   u64 nids, u32 keep_listed, u32* flags) {
   const u64 i = (u64)blockIdx.x * WG + threadIdx.x;
   if (i >= n) return;
   const u32 v = lead[i];
@@ -659,7 +659,20 @@ __global__ __launch_bounds__(WG) void k_keep_flags(const u32* lead, u64 n, const
     u64 mid = lo + ((hi - lo) >> 1);
     if (ids[mid] < v) lo = mid + 1; else hi = mid;
   }
-  flags[i] = (lo < nids && ids[lo] == v) ? 0u : 1u;
+  const u32 listed = (lo < nids && ids[lo] == v) ? 1u : 0u;
+  flags[i] = listed == keep_listed ? 1u : 0u;
+}
+
+// Adjacent rows i-1, i with row i-1 >= row i (lexicographic): counted.
+__global__ __launch_bounds__(WG) void k_order_violations(ColsIn a, u32 k, u64 n, u64* bad) {
+  const u64 i = (u64)blockIdx.x * WG + threadIdx.x;
+  if (i == 0 || i >= n) return;
+  int cmp = 0;
+  for (u32 j = 0; j < k && cmp == 0; ++j) {
+    const u32 x = a.c[j][i - 1], y = a.c[j][i];
+    cmp = x < y ? -1 : (x > y ? 1 : 0);
+  }
+  if (cmp >= 0) atomicAdd(reinterpret_cast<unsigned long long*>(bad), 1ull);
 }
 
 __global__ void k_lead_range(const u32* col, u64 n, u32 v, u64* out) {
@@ -724,13 +737,26 @@ u64 compact_flagged(Ctx c, u32 k, const ColsIn& a, u64 n, const u32* flags, cons
   return h;
 }
 
-u64 drop_leading(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32 lead_col, const u32* ids,
-                 u64 nids, u32* const* out_cols) {
+u64 select_leading(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32 lead_col, const u32* ids,
+                   u64 nids, bool keep_listed, u32* const* out_cols) {
   if (n == 0) return 0;
   DBuf<u32> flags(c.mem, n);
-  k_keep_flags<<<grid_for(n, WG), WG, 0, c.s>>>(in_cols[lead_col], n, ids, nids, flags.get());
+  k_keep_flags<<<grid_for(n, WG), WG, 0, c.s>>>(in_cols[lead_col], n, ids, nids,
+                                                 keep_listed ? 1u : 0u, flags.get());
   WCDL_HIP(hipGetLastError());
   return compact_flagged(c, k, cols_in(k, in_cols), n, flags.get(), cols_out(k, out_cols));
+}
+
+u64 order_violations(Ctx c, u32 k, const u32* const* cols, u64 n) {
+  if (n < 2) return 0;
+  DBuf<u64> bad(c.mem, 1);
+  fill_u64(c, bad.get(), 1, 0);
+  k_order_violations<<<grid_for(n, WG), WG, 0, c.s>>>(cols_in(k, cols), k, n, bad.get());
+  WCDL_HIP(hipGetLastError());
+  u64 h = 0;
+  WCDL_HIP(hipMemcpyAsync(&h, bad.get(), sizeof(u64), hipMemcpyDeviceToHost, c.s));
+  WCDL_HIP(hipStreamSynchronize(c.s));
+  return h;
 }
 
 void lead_range(Ctx c, const u32* col, u64 n, u32 v, u64* d_out) {

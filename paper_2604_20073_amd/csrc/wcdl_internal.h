@@ -283,10 +283,13 @@ void merge_disjoint(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const*
                     u32* const* out);
 // Rows of sorted column `col` equal to v: d_out[0] = first, d_out[1] = end.
 void lead_range(Ctx c, const u32* col, u64 n, u32 v, u64* d_out);
-// Keep the rows whose column `lead_col` is not in the sorted list ids[0..nids);
-// returns the count kept (synchronises).
-u64 drop_leading(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32 lead_col, const u32* ids,
-                 u64 nids, u32* const* out_cols);
+// Keep the rows whose column `lead_col` is (keep_listed) or is not (else) in
+// the sorted list ids[0..nids); returns the count kept (synchronises).
+u64 select_leading(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32 lead_col, const u32* ids,
+                   u64 nids, bool keep_listed, u32* const* out_cols);
+// Adjacent row pairs of a k-column run that are not strictly ascending
+// (lexicographically): 0 for a sorted, duplicate-free run (synchronises).
+u64 order_violations(Ctx c, u32 k, const u32* const* cols, u64 n);
 // Fill helpers.
 void fill_u32(Ctx c, u32* p, u64 n, u32 v);
 void fill_u64(Ctx c, u64* p, u64 n, u64 v);

@@ -227,66 +227,77 @@ __device__ inline u32 owner_item(const u64* pre, u32 n, u64 g) {
 // narrowed range.
 __device__ inline bool try_candidate(const DPlan* P, const Bufs& B, int L, u32 i, u32 v, u32 drv,
                                      u32 r, u32 dhi, R8& slo, R8& shi) {
+  // A per-lane flag instead of early returns: a lane-divergent return inside
+  // a loop whose trip count comes from the plan has been seen to be skipped
+  // on this target, so every test below clears `ok` and later work is
+  // guarded by it.
   const DLevel& lv = P->lvl[L];
-  for (u32 f = 0; f < lv.nne; ++f)
-    if (v == operand(B, lv.ne[f], L, i, v)) return false;
+  u32 ok = 1;
+  for (u32 f = 0; f < lv.nne; ++f) ok &= v != operand(B, lv.ne[f], L, i, v) ? 1u : 0u;
   if (L == 0) {
     // An atom without matches under its constants empties the rule.
-    for (u32 a = 0; a < P->natoms; ++a)
-      if (B.rng0[2 * a] >= B.rng0[2 * a + 1]) return false;
+    for (u32 a = 0; a < P->natoms; ++a) ok &= B.rng0[2 * a] < B.rng0[2 * a + 1] ? 1u : 0u;
     // Level-0 values come straight from the root keys, so their bounds
     // (constants only) are checked here; deeper levels clip candidate
     // ranges to their bounds instead (prepare_item).
     for (u32 b = 0; b < lv.nbnd; ++b) {
       const u32 x = lv.bnd[b].o.v, adj = lv.bnd[b].adj;
-      if (!lv.bnd[b].is_hi) {
-        if (x > UMAX - adj || v < x + adj) return false;
-      } else {
-        if (x < adj || v > x - adj) return false;
-      }
+      if (!lv.bnd[b].is_hi)
+        ok &= (x <= UMAX - adj && v >= x + adj) ? 1u : 0u;
+      else
+        ok &= (x >= adj && v <= x - adj) ? 1u : 0u;
     }
   }
 #pragma unroll
   for (int s = 0; s < MAXS; ++s) {
-    if (s < (int)lv.nsrc) {
+    if (s < (int)lv.nsrc && ok) {
       const DSource& src = lv.src[s];
       const u32* col = src.col;
       const u32 a = src.atom;
       const bool last = src.last != 0;
-      u32 lo, hi;
+      u32 lo = 0, hi = 0;
       if ((u32)s == drv) {
         lo = B.lo(L - 1, a, i);
         // Only the first row of a run of equal values yields the candidate.
-        if (!last && r > lo && ldg(col + r - 1) == v) return false;
-        hi = B.hi(L - 1, a, i);
-        lo = r;
-        if (last) hi = r + 1;
-        else if (dhi != NONE) hi = dhi;
-        else if (src.dir) hi = ldg(src.dir + v + 1);
-        else hi = gallop_past(col, r + 1, hi, v);
+        if (!last && r > lo && ldg(col + r - 1) == v) {
+          ok = 0;
+        } else {
+          hi = B.hi(L - 1, a, i);
+          lo = r;
+          if (last) hi = r + 1;
+          else if (dhi != NONE) hi = dhi;
+          else if (src.dir) hi = ldg(src.dir + v + 1);
+          else hi = gallop_past(col, r + 1, hi, v);
+        }
       } else if (src.alias != NONE) {
         // Same column and same range as an earlier source: same result.
         lo = slo.get(src.alias);
         hi = shi.get(src.alias);
       } else if (src.dir) {
         // Unnarrowed first column: the directory gives the run directly.
-        if (v > src.dmax) return false;
-        lo = ldg(src.dir + v);
-        hi = ldg(src.dir + v + 1);
-        if (lo >= hi) return false;
+        if (v > src.dmax) {
+          ok = 0;
+        } else {
+          lo = ldg(src.dir + v);
+          hi = ldg(src.dir + v + 1);
+          if (lo >= hi) ok = 0;
+        }
       } else {
         lo = B.lo(L - 1, a, i);
         hi = B.hi(L - 1, a, i);
-        u32 p = lower_bound_u32(col, lo, hi, v);
-        if (p >= hi || ldg(col + p) != v) return false;
-        lo = p;
-        hi = last ? p + 1 : gallop_past(col, p + 1, hi, v);
+        const u32 p = lower_bound_u32(col, lo, hi, v);
+        if (p >= hi || ldg(col + p) != v) {
+          ok = 0;
+        } else {
+          lo = p;
+          hi = last ? p + 1 : gallop_past(col, p + 1, hi, v);
+        }
       }
       slo.put(s, lo);
       shi.put(s, hi);
     }
   }
-  return true;
+  return ok != 0;
 }
 
 // Range of atom a after binding level L (narrowed if the atom is a source).
@@ -307,24 +318,28 @@ __device__ inline void new_range(const DPlan* P, const Bufs& B, int L, u32 i, u3
 // its clipped candidate rows [clo, chi) for the new item.
 __device__ inline bool prepare_item(const DPlan* P, const Bufs& B, int L, u32 i, u32 v,
                                     const R8& slo, const R8& shi, u32* drv, u32* clo, u32* chi) {
+  // Per-lane flag, no early returns inside the plan-driven loops (see
+  // try_candidate).
   const DLevel& nx = P->lvl[L + 1];
-  u32 lov = 0, hiv = UMAX;
+  u32 lov = 0, hiv = UMAX, ok = 1;
   for (u32 b = 0; b < nx.nbnd; ++b) {
-    u32 x = operand(B, nx.bnd[b].o, L, i, v);
-    u32 adj = nx.bnd[b].adj;
+    const u32 x = operand(B, nx.bnd[b].o, L, i, v);
+    const u32 adj = nx.bnd[b].adj;
     if (!nx.bnd[b].is_hi) {
-      if (x > UMAX - adj) return false;
-      lov = max(lov, x + adj);
+      ok &= x <= UMAX - adj ? 1u : 0u;
+      const u32 t = x + adj;
+      lov = t > lov ? t : lov;
     } else {
-      if (x < adj) return false;
-      hiv = min(hiv, x - adj);
+      ok &= x >= adj ? 1u : 0u;
+      const u32 t = x - adj;
+      hiv = t < hiv ? t : hiv;
     }
   }
-  if (lov > hiv) return false;
+  ok &= lov <= hiv ? 1u : 0u;
   const bool clip = lov != 0 || hiv != UMAX;
   u32 best = 0, bsz = UMAX, blo = 0, bhi = 0;
   for (u32 s = 0; s < nx.nsrc; ++s) {
-    if (nx.src[s].alias != NONE) continue;  // same range as an earlier source
+    if (nx.src[s].alias != NONE || !ok) continue;  // aliases: same range as an earlier source
     u32 lo, hi;
     new_range(P, B, L, i, nx.src[s].atom, slo, shi, &lo, &hi);
     if (clip) {
@@ -338,8 +353,9 @@ __device__ inline bool prepare_item(const DPlan* P, const Bufs& B, int L, u32 i,
         if (hiv != UMAX) hi = upper_bound_u32(src.col, lo, hi, hiv);
       }
     }
-    if (lo >= hi) return false;  // no value can satisfy this source
-    if (hi - lo < bsz) {
+    if (lo >= hi) {
+      ok = 0;  // no value can satisfy this source
+    } else if (hi - lo < bsz) {
       bsz = hi - lo;
       best = s;
       blo = lo;
@@ -349,7 +365,7 @@ __device__ inline bool prepare_item(const DPlan* P, const Bufs& B, int L, u32 i,
   *drv = best;
   *clo = blo;
   *chi = bhi;
-  return true;
+  return ok != 0;
 }
 
 __device__ inline void store_item(const DPlan* P, const Bufs& B, int L, u32 i, u32 v, u32 pos,

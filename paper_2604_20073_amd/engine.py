@@ -32,11 +32,12 @@ WCDL_F_BATCHED = 0x10
 WCDL_F_HEAD_BODY_OFF = 0x20
 WCDL_F_RUN_BITMAPS_OFF = 0x40
 WCDL_F_GROUPED_SORT_OFF = 0x80
+WCDL_F_CHECKED = 0x200
 PHASES = ["histogram", "count", "materialize", "delta", "index", "merge", "load", "other"]
 KERNELS = ["join_count", "join_materialize", "join_histogram", "unused"]
 ERRORS = {-1: "E_INVALID", -2: "E_ARITY", -3: "E_UNKNOWN_REL", -4: "E_UNSAFE_RULE",
           -5: "E_UNSUPPORTED", -6: "E_STATE", -7: "E_NOMEM", -8: "E_BUDGET", -9: "E_DEVICE",
-          -10: "E_PARSE"}
+          -10: "E_PARSE", -11: "E_CHECK"}
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -68,6 +69,28 @@ class _StepStats(ctypes.Structure):
                 ("resident_rows", ctypes.c_uint64), ("wall_ms", ctypes.c_double)]
 
 
+class _Term(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("value", ctypes.c_uint32)]
+
+
+class _Atom(ctypes.Structure):
+    _fields_ = [("rel", ctypes.c_uint32), ("arity", ctypes.c_uint32),
+                ("terms", ctypes.POINTER(_Term))]
+
+
+class _Cmp(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("lhs", _Term), ("rhs", _Term)]
+
+
+class _Rule(ctypes.Structure):
+    _fields_ = [("head", _Atom), ("n_body", ctypes.c_uint32), ("body", ctypes.POINTER(_Atom)),
+                ("n_cmp", ctypes.c_uint32), ("cmp", ctypes.POINTER(_Cmp)),
+                ("n_vars", ctypes.c_uint32), ("var_order", ctypes.POINTER(ctypes.c_uint32))]
+
+
+_CMP_OPS = {"<": 0, "<=": 1, "!=": 2, ">": 3, ">=": 4}
+
+
 class WcdlError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
@@ -84,6 +107,8 @@ EXPORTS = [
     "wcdl_owner_key", "wcdl_decode_unit", "wcdl_relation_range", "wcdl_read_rows",
     "wcdl_autotune", "wcdl_serve_begin", "wcdl_serve_admit", "wcdl_serve_step",
     "wcdl_serve_live", "wcdl_serve_release", "wcdl_serve_end",
+    "wcdl_instance_create", "wcdl_instance_id", "wcdl_instance_load", "wcdl_instance_size",
+    "wcdl_instance_read", "wcdl_instance_destroy", "wcdl_run_batch", "wcdl_step",
 ]
 
 
@@ -107,6 +132,17 @@ def lib():
     L.wcdl_load_columns.argtypes = [P, u32, ctypes.POINTER(P), u64, ctypes.c_int]
     L.wcdl_clear_relation.argtypes = [P, u32]
     L.wcdl_add_rules_text.argtypes = [P, ctypes.c_char_p]
+    L.wcdl_add_rule.argtypes = [P, ctypes.POINTER(_Rule), pu32]
+    L.wcdl_instance_create.argtypes = [P, ctypes.POINTER(P)]
+    L.wcdl_instance_id.argtypes = [P]
+    L.wcdl_instance_id.restype = u32
+    L.wcdl_instance_load.argtypes = [P, u32, ctypes.POINTER(P), u64, ctypes.c_int]
+    L.wcdl_instance_size.argtypes = [P, u32, pu64]
+    L.wcdl_instance_read.argtypes = [P, u32, ctypes.POINTER(P), u64, pu64, ctypes.c_int]
+    L.wcdl_instance_destroy.argtypes = [P]
+    L.wcdl_instance_destroy.restype = None
+    L.wcdl_run_batch.argtypes = [P, ctypes.POINTER(P), u32, ctypes.POINTER(_Stats)]
+    L.wcdl_step.argtypes = [P, ctypes.POINTER(P), u32, ctypes.POINTER(ctypes.c_uint8), pu64]
     L.wcdl_rule_count.argtypes = [P, pu32]
     L.wcdl_split_rule.argtypes = [P, u32, pu32, u32, pu32]
     L.wcdl_run.argtypes = [P, ctypes.POINTER(_Stats)]
@@ -241,6 +277,60 @@ class Engine:
     def add_rules(self, text: str):
         self._check(self._lib.wcdl_add_rules_text(self._e, text.encode()))
 
+    def add_rule(self, head, body, cmps=(), var_order=None) -> int:
+        """Register one rule given as data (wcdl_add_rule): head and body
+        atoms are (relation name, terms); a term is a variable name (str) or
+        a constant (int); cmps are (op, a, b) with op in < <= != > >=;
+        var_order lists every body variable once (None: planner's choice)."""
+        names = {}
+
+        def term(t):
+            if isinstance(t, str):
+                return _Term(0, names.setdefault(t, len(names)))
+            return _Term(1, int(t))
+
+        keep = []
+
+        def atom(a):
+            rel, terms = a
+            arr = (_Term * max(len(terms), 1))(*[term(t) for t in terms])
+            keep.append(arr)
+            return _Atom(self.ids[rel], len(terms), arr)
+
+        h = atom(head)
+        b = (_Atom * len(body))(*[atom(a) for a in body])
+        c = (_Cmp * max(len(cmps), 1))(*[_Cmp(_CMP_OPS[op], term(x), term(y)) for op, x, y in cmps])
+        r = _Rule(h, len(body), b, len(cmps), c, 0, None)
+        if var_order is not None:
+            vo = (ctypes.c_uint32 * len(var_order))(*[names[v] for v in var_order])
+            keep.append(vo)
+            r.n_vars = len(var_order)
+            r.var_order = vo
+        rid = ctypes.c_uint32()
+        self._check(self._lib.wcdl_add_rule(self._e, ctypes.byref(r), ctypes.byref(rid)))
+        return rid.value
+
+    # -- instances (batched engines) -------------------------------------------
+    def instance(self) -> "Instance":
+        h = ctypes.c_void_p()
+        self._check(self._lib.wcdl_instance_create(self._e, ctypes.byref(h)))
+        return Instance(self, h)
+
+    def run_batch(self, instances) -> dict:
+        arr = (ctypes.c_void_p * max(len(instances), 1))(*[i._h for i in instances])
+        s = _Stats()
+        self._check(self._lib.wcdl_run_batch(self._e, arr, len(instances), ctypes.byref(s)))
+        return self._stats(s)
+
+    def step(self, instances):
+        """One serving round for these instances: (done flags, next bound bytes)."""
+        n = len(instances)
+        arr = (ctypes.c_void_p * max(n, 1))(*[i._h for i in instances])
+        done = (ctypes.c_uint8 * max(n, 1))()
+        nb = ctypes.c_uint64()
+        self._check(self._lib.wcdl_step(self._e, arr, n, done, ctypes.byref(nb)))
+        return [bool(done[i]) for i in range(n)], nb.value
+
     def rule_count(self) -> int:
         n = ctypes.c_uint32()
         self._check(self._lib.wcdl_rule_count(self._e, ctypes.byref(n)))
@@ -324,6 +414,10 @@ class Engine:
     def run(self) -> dict:
         s = _Stats()
         self._check(self._lib.wcdl_run(self._e, ctypes.byref(s)))
+        return self._stats(s)
+
+    @staticmethod
+    def _stats(s) -> dict:
         return {"rounds": s.rounds, "derived_rows": s.derived_rows,
                 "candidate_rows": s.candidate_rows, "join_units": s.join_units,
                 "wall_ms": s.wall_ms, "phase_ms": dict(zip(PHASES, list(s.phase_ms))),
@@ -393,3 +487,50 @@ class Engine:
         self._check(self._lib.wcdl_delta_sizes(self._e, self.ids[name], buf, cnt.value,
                                                ctypes.byref(cnt)))
         return [int(buf[i]) for i in range(cnt.value)]
+
+
+class Instance:
+    """One instance of a batched engine's program (wcdl_instance)."""
+
+    def __init__(self, engine: Engine, handle):
+        self.engine = engine
+        self._h = handle
+        self.id = int(engine._lib.wcdl_instance_id(handle))
+
+    def _cols(self, name, rows):
+        k = self.engine.arity[name] - 1  # declared arity (the instance column is added)
+        torch = self.engine._torch
+        if isinstance(rows, torch.Tensor):
+            t = rows.reshape(-1, k)
+            cols = [t[:, j].contiguous() for j in range(k)]
+            return (ctypes.c_void_p * k)(*[c.data_ptr() for c in cols]), t.shape[0], \
+                (1 if t.is_cuda else 0), cols
+        a = np.asarray(rows, dtype=np.uint32).reshape(-1, k)
+        cols = [np.ascontiguousarray(a[:, j]) for j in range(k)]
+        return (ctypes.c_void_p * k)(*[c.ctypes.data for c in cols]), a.shape[0], 0, cols
+
+    def load(self, name: str, rows):
+        arr, n, on_dev, keep = self._cols(name, rows)
+        e = self.engine
+        e._check(e._lib.wcdl_instance_load(self._h, e.ids[name], arr, n, on_dev))
+        del keep
+
+    def size(self, name: str) -> int:
+        e = self.engine
+        n = ctypes.c_uint64()
+        e._check(e._lib.wcdl_instance_size(self._h, e.ids[name], ctypes.byref(n)))
+        return n.value
+
+    def read_numpy(self, name: str) -> np.ndarray:
+        e = self.engine
+        k, n = e.arity[name] - 1, self.size(name)
+        out = np.empty((k, max(n, 1)), dtype=np.uint32)
+        arr = (ctypes.c_void_p * k)(*[out[j].ctypes.data for j in range(k)])
+        w = ctypes.c_uint64()
+        e._check(e._lib.wcdl_instance_read(self._h, e.ids[name], arr, n, ctypes.byref(w), 0))
+        return np.ascontiguousarray(out[:, :n].T)
+
+    def destroy(self):
+        if self._h:
+            self.engine._lib.wcdl_instance_destroy(self._h)
+            self._h = None
