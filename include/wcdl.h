@@ -375,6 +375,16 @@ wcdl_status wcdl_serve_step(wcdl_engine* e, wcdl_step_stats* stats);
  * An admitted instance absent from this list has reached its fixpoint. */
 wcdl_status wcdl_serve_live(wcdl_engine* e, uint32_t* ids, uint64_t cap, uint64_t* count);
 
+/* wcdl_serve_live without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops): its
+ * kernels work in a fixed static device array of about 4.5 MB per GPU, held
+ * until the process ends.  Limits: instance ids below 2^22 (else
+ * WCDL_E_UNSUPPORTED) and at most 2^20 live instances (else
+ * WCDL_E_UNSUPPORTED; *count is not written).  Results equal
+ * wcdl_serve_live's.  All engines on one GPU share the array: calls that
+ * overlap on one GPU (from several host threads) race. */
+wcdl_status wcdl_serve_live_static(wcdl_engine* e, uint32_t* ids, uint64_t cap, uint64_t* count);
+
 /* Drop every row of the listed instances from every relation (frees their
  * memory).  ids need not be sorted. */
 wcdl_status wcdl_serve_release(wcdl_engine* e, const uint32_t* ids, uint64_t n);

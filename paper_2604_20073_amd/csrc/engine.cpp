@@ -16,6 +16,86 @@
 namespace wcdl {
 
 // ===========================================================================
+// Static scratch of the allocation-free live-instance listing
+// ===========================================================================
+//
+// wcdl_serve_live_static lists the live instances of a serving engine without
+// allocating: its kernels work in this fixed device array (one copy per GPU,
+// held until the process ends).  Layout in 32-bit words: [0] ids listed,
+// [1] set if some id is >= LIVE_MAX_IDS; from LIVE_BITMAP_AT one bit per
+// instance id below LIVE_MAX_IDS; from LIVE_LIST_AT at most LIVE_MAX_LIST ids.
+constexpr u32 LIVE_MAX_IDS = 1u << 22;
+constexpr u32 LIVE_MAX_LIST = 1u << 20;
+constexpr u32 LIVE_BITMAP_AT = 64;
+constexpr u32 LIVE_LIST_AT = LIVE_BITMAP_AT + LIVE_MAX_IDS / 32;
+constexpr u32 LIVE_SCRATCH_WORDS = LIVE_LIST_AT + LIVE_MAX_LIST;
+
+static __device__ __align__(256) u32 scratch[LIVE_SCRATCH_WORDS];
+
+// Device address of `scratch` on each GPU (the host-side name is not one);
+// looked up once per device when an engine is created there.
+constexpr int MAX_DEVICES = 64;
+u32* scratch_at[MAX_DEVICES] = {};
+
+void ensure_scratch_address(int device) {
+  if (device < 0 || device >= MAX_DEVICES) throw Error(WCDL_E_INVALID, "device ordinal out of range");
+  if (scratch_at[device]) return;
+  void* p = nullptr;
+  WCDL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  scratch_at[device] = static_cast<u32*>(p);
+}
+
+// Clear the counters and the bitmap (a kernel rather than a memset).
+__global__ void k_live_clear(u32* sc) {
+  for (u64 w = (u64)blockIdx.x * blockDim.x + threadIdx.x; w < LIVE_LIST_AT;
+       w += (u64)gridDim.x * blockDim.x)
+    sc[w] = 0;
+}
+
+// Set the bit of every distinct leading value of a sorted column.
+__global__ void k_live_mark(const u32* col, u64 n, u32* sc) {
+  const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || (i > 0 && col[i] == col[i - 1])) return;
+  const u32 v = col[i];
+  if (v >= LIVE_MAX_IDS) {
+    atomicOr(&sc[1], 1u);
+    return;
+  }
+  atomicOr(&sc[LIVE_BITMAP_AT + (v >> 5)], 1u << (v & 31u));
+}
+
+// One workgroup of 1,024 threads lists the set bits in ascending order:
+// thread t owns a contiguous stretch of bitmap words.
+__global__ __launch_bounds__(1024) void k_live_list(u32* sc) {
+  constexpr u32 T = 1024, W = LIVE_MAX_IDS / 32 / T;
+  __shared__ u32 part[T];
+  const u32 t = threadIdx.x;
+  const u32* bm = sc + LIVE_BITMAP_AT + t * W;
+  u32 c = 0;
+  for (u32 w = 0; w < W; ++w) c += __popc(bm[w]);
+  part[t] = c;
+  __syncthreads();
+  // Exclusive prefix over the threads (Hillis-Steele in LDS).
+  for (u32 d = 1; d < T; d <<= 1) {
+    const u32 x = t >= d ? part[t - d] : 0u;
+    __syncthreads();
+    part[t] += x;
+    __syncthreads();
+  }
+  u32 at = part[t] - c;
+  if (t == T - 1) sc[0] = part[t];
+  for (u32 w = 0; w < W; ++w) {
+    u32 bits = bm[w];
+    while (bits) {
+      const u32 b = __ffs(bits) - 1;
+      bits &= bits - 1;
+      if (at < LIVE_MAX_LIST) sc[LIVE_LIST_AT + at] = (t * W + w) * 32 + b;
+      ++at;
+    }
+  }
+}
+
+// ===========================================================================
 // Device memory cache
 // ===========================================================================
 
@@ -2266,6 +2346,7 @@ wcdl_status wcdl_create(const wcdl_config* cfg, wcdl_engine** out) {
     }
     e->cfg.streams = nullptr;
     e->mem.reset(new DeviceMemory(e->cfg.alloc, e->streams[0]));
+    ensure_scratch_address(e->cfg.device);
   });
   if (st != WCDL_OK) {
     std::fprintf(stderr, "wcdl_create: %s\n", e->err.c_str());
@@ -2704,6 +2785,47 @@ wcdl_status wcdl_serve_live(wcdl_engine* e, uint32_t* ids, uint64_t cap, uint64_
       ++i;
     }
     if (count) *count = live.size();
+  });
+}
+
+wcdl_status wcdl_serve_live_static(wcdl_engine* e, uint32_t* ids, uint64_t cap, uint64_t* count) {
+  return guarded(e, [&] {
+    if (!e->serving) throw Error(WCDL_E_STATE, "not serving");
+    u32* sc = scratch_at[e->cfg.device];
+    if (!sc) throw Error(WCDL_E_STATE, "static scratch not set up on this device");
+    hipStream_t s = e->streams[0];
+    // Work of every stream is done before the columns are read.
+    for (auto st : e->streams) WCDL_HIP(hipStreamSynchronize(st));
+    k_live_clear<<<128, 256, 0, s>>>(sc);
+    WCDL_HIP(hipGetLastError());
+    auto mark = [&](const Cols& c) {
+      if (c.n == 0 || c.order.empty() || c.order[0] != 0) return;
+      const u64 blocks = (c.n + 255) / 256;
+      if (blocks > 0x7fffffffull) throw Error(WCDL_E_UNSUPPORTED, "relation too large");
+      k_live_mark<<<(u32)blocks, 256, 0, s>>>(c.col[0].get(), c.n, sc);
+      WCDL_HIP(hipGetLastError());
+    };
+    for (auto& R : e->rels)
+      for (auto& kv : R.delta_ord) mark(kv.second);
+    for (auto& kv : e->pending) mark(kv.second);
+    k_live_list<<<1, 1024, 0, s>>>(sc);
+    WCDL_HIP(hipGetLastError());
+    u32 head[2] = {0, 0};
+    WCDL_HIP(hipMemcpyAsync(head, sc, sizeof(head), hipMemcpyDeviceToHost, s));
+    WCDL_HIP(hipStreamSynchronize(s));
+    if (head[1])
+      throw Error(WCDL_E_UNSUPPORTED, "an instance id is >= " + std::to_string(LIVE_MAX_IDS) +
+                                          ", beyond the static listing's bitmap");
+    if (head[0] > LIVE_MAX_LIST)
+      throw Error(WCDL_E_UNSUPPORTED, std::to_string(head[0]) + " live instances exceed the static "
+                                      "list of " + std::to_string(LIVE_MAX_LIST));
+    const u64 n = std::min<u64>(head[0], cap);
+    if (n && !ids) throw Error(WCDL_E_INVALID, "null ids");
+    if (n) {
+      WCDL_HIP(hipMemcpyAsync(ids, sc + LIVE_LIST_AT, n * sizeof(u32), hipMemcpyDeviceToHost, s));
+      WCDL_HIP(hipStreamSynchronize(s));
+    }
+    if (count) *count = head[0];
   });
 }
 

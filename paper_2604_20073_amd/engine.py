@@ -109,6 +109,7 @@ EXPORTS = [
     "wcdl_serve_live", "wcdl_serve_release", "wcdl_serve_end",
     "wcdl_instance_create", "wcdl_instance_id", "wcdl_instance_load", "wcdl_instance_size",
     "wcdl_instance_read", "wcdl_instance_destroy", "wcdl_run_batch", "wcdl_step",
+    "wcdl_serve_live_static",
 ]
 
 
@@ -156,6 +157,7 @@ def lib():
     L.wcdl_serve_admit.argtypes = [P, u32, ctypes.POINTER(P), u64, ctypes.c_int]
     L.wcdl_serve_step.argtypes = [P, ctypes.POINTER(_StepStats)]
     L.wcdl_serve_live.argtypes = [P, pu32, u64, pu64]
+    L.wcdl_serve_live_static.argtypes = [P, pu32, u64, pu64]
     L.wcdl_serve_release.argtypes = [P, pu32, u64]
     L.wcdl_serve_end.argtypes = [P]
     L.wcdl_work_slice.argtypes = [u64, u64, u64, pu64, pu64]
@@ -398,6 +400,14 @@ class Engine:
         self._check(self._lib.wcdl_serve_live(self._e, None, 0, ctypes.byref(cnt)))
         buf = (ctypes.c_uint32 * max(cnt.value, 1))()
         self._check(self._lib.wcdl_serve_live(self._e, buf, cnt.value, ctypes.byref(cnt)))
+        return [int(buf[i]) for i in range(cnt.value)]
+
+    def serve_live_static(self) -> list:
+        """serve_live through the allocation-free entry point."""
+        cnt = ctypes.c_uint64()
+        self._check(self._lib.wcdl_serve_live_static(self._e, None, 0, ctypes.byref(cnt)))
+        buf = (ctypes.c_uint32 * max(cnt.value, 1))()
+        self._check(self._lib.wcdl_serve_live_static(self._e, buf, cnt.value, ctypes.byref(cnt)))
         return [int(buf[i]) for i in range(cnt.value)]
 
     def serve_release(self, ids):
