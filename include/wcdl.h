@@ -1,8 +1,9 @@
 /*
  * wcdl.h -- C ABI of the worst-case-optimal Datalog engine for AMD MI355X.
  *
- * The engine evaluates positive Datalog programs (Horn clauses, paper Sec. 2
- * "Datalog") to their least fixpoint by semi-naive evaluation (Sec. 2, the
+ * The engine evaluates Datalog programs (Horn clauses, paper Sec. 2
+ * "Datalog"; stratified negation, Tab. 1) to their least fixpoint, stratum
+ * by stratum, by semi-naive evaluation (Sec. 2, the
  * differential form of the fixpoint), running every multi-way rule body as a
  * worst-case-optimal join over flat, sorted, columnar uint32 relations
  * (Sec. 2 "Join Processing", Sec. 4).  Each iteration follows the staged
@@ -60,6 +61,7 @@ typedef int32_t wcdl_status;
 #define WCDL_MAX_BODY 8
 #define WCDL_MAX_VARS 8
 #define WCDL_MAX_CMPS 8
+#define WCDL_MAX_NEG 4
 
 /* Configuration flags (wcdl_config.flags). */
 #define WCDL_F_BALANCE_OFF 0x1u  /* one root key per workgroup instead of the
@@ -217,8 +219,13 @@ typedef struct {
   wcdl_term rhs;
 } wcdl_cmp;
 
-/* Head(...) <- Body_1(...), ..., Body_n(...), comparisons (Sec. 2).  Every
- * head and comparison variable must occur in a body atom (safety).
+/* Head(...) <- Body_1(...), ..., Body_n(...), comparisons, not Neg_1(...),
+ * ..., not Neg_k(...) (Sec. 2; negation as in Tab. 1, stratified).  Every
+ * head, comparison and negated-atom variable must occur in a (positive) body
+ * atom (safety).  A negated atom's relation must not depend on the head's
+ * relation (the program stays stratifiable); a binding of the body yields
+ * the head only if no negated atom's tuple is in its relation, which is
+ * complete when the rule runs (it belongs to a lower stratum).
  * var_order, if not NULL, fixes the join's variable order (n_vars entries,
  * each body variable exactly once); NULL lets the planner choose (delta
  * relation outermost, Sec. 7.3). */
@@ -230,17 +237,21 @@ typedef struct {
   const wcdl_cmp* cmp;
   uint32_t n_vars;
   const uint32_t* var_order;
+  uint32_t n_neg;            /* negated atoms (at most WCDL_MAX_NEG) */
+  const wcdl_atom* neg;
 } wcdl_rule;
 
 /* Register one rule; *rule_id receives its id.  Rejected with
  * WCDL_E_UNSAFE_RULE, WCDL_E_ARITY, WCDL_E_UNKNOWN_REL or
- * WCDL_E_UNSUPPORTED (limits above). */
+ * WCDL_E_UNSUPPORTED (limits above, or a negated atom whose relation
+ * depends on the head's: the program would not be stratifiable). */
 wcdl_status wcdl_add_rule(wcdl_engine* e, const wcdl_rule* rule, uint32_t* rule_id);
 
 /* Register rules from text, e.g.
  *   "path(x,y) :- edge(x,y).  path(x,z) :- path(x,y), edge(y,z), x != z."
  * Identifiers in argument position are variables ("_" is anonymous),
- * decimal numbers are constants, comparisons are < <= > >= !=, and '%' or
+ * decimal numbers are constants, comparisons are < <= > >= !=, a body item
+ * "!rel(...)" is a negated atom, and '%' or
  * '//' starts a comment.  Relations must be declared first.  A ground clause
  * without a body adds a fact.  All-or-nothing: on error no rule is added. */
 wcdl_status wcdl_add_rules_text(wcdl_engine* e, const char* text);
@@ -342,6 +353,7 @@ wcdl_status wcdl_autotune(wcdl_engine* e, const uint32_t* wg_per_cu, uint32_t n,
 
 /* ---- Continuous evaluation (serving), batched engines only -------------
  *
+ * Programs with negation cannot be served (WCDL_E_UNSUPPORTED).
  * A positive program's least model is also reached by one semi-naive loop
  * over all rules in which every relation, input relations included, has a
  * delta (Sec. 2's differential form; stratification is only an evaluation

@@ -208,6 +208,7 @@ struct Rule {
   Atom head;
   std::vector<Atom> body;
   std::vector<Cmp> cmps;
+  std::vector<Atom> negs;  // negated atoms (stratified negation)
   u32 nvars = 0;
   std::vector<u32> var_order;  // optional user order (original variable ids)
   // Helper-relation splitting: the body as registered, and where each of its
@@ -491,6 +492,7 @@ struct Version {
   bool dead = false;            // a comparison between constants fails
   std::vector<u32> level_var;   // variable id at each level
   std::vector<AtomUse> atoms;
+  std::vector<AtomUse> negs;    // negated atoms, in the order of DPlan::neg
   std::vector<std::vector<u32>> src_pos;  // per level, per source: column position in its atom
   std::vector<std::vector<bool>> want_dir;  // per level, per source: unnarrowed first column
   DPlan plan{};                 // pointers filled at evaluation time
@@ -848,6 +850,49 @@ Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
     }
     P.xprod = xp ? 1u : 0u;
   }
+  // Negated atoms: searched in a copy ordered constants first, then
+  // variables by level, at the level that binds their last variable.
+  {
+    struct NegPlan { u32 level; AtomUse u; };
+    std::vector<NegPlan> np;
+    for (const Atom& a : r.negs) {
+      NegPlan x;
+      x.u.rel = a.rel;
+      std::vector<u32> cols(a.t.size());
+      std::iota(cols.begin(), cols.end(), 0u);
+      std::stable_sort(cols.begin(), cols.end(), [&](u32 c1, u32 c2) {
+        int k1 = a.t[c1].var ? level_of[a.t[c1].v] : -1;
+        int k2 = a.t[c2].var ? level_of[a.t[c2].v] : -1;
+        return k1 < k2;
+      });
+      x.level = 0;
+      for (u32 c : cols) {
+        x.u.order.push_back(c);
+        x.u.pos_var.push_back(a.t[c].var ? (int)a.t[c].v : -1);
+        x.u.pos_const.push_back(a.t[c].var ? 0u : a.t[c].v);
+        if (a.t[c].var) x.level = std::max<u32>(x.level, (u32)level_of[a.t[c].v]);
+      }
+      np.push_back(x);
+    }
+    std::stable_sort(np.begin(), np.end(), [](const NegPlan& a, const NegPlan& b) { return a.level < b.level; });
+    P.nneg = (u32)np.size();
+    for (u32 k = 0; k < np.size(); ++k) {
+      DNeg& ng = P.neg[k];
+      ng.ncols = (u32)np[k].u.order.size();
+      ng.level = np[k].level;
+      for (u32 j = 0; j < ng.ncols; ++j) {
+        const int pv = np[k].u.pos_var[j];
+        ng.val[j].is_var = pv >= 0 ? 1u : 0u;
+        ng.val[j].v = pv >= 0 ? (u32)level_of[pv] : np[k].u.pos_const[j];
+      }
+      P.lvl[ng.level].nneg++;
+      v.negs.push_back(np[k].u);
+    }
+    if (P.nneg) {
+      P.xprod = 0;
+      if (P.lvl[m - 1].nneg) P.leaf_fast = 0;
+    }
+  }
   // LDS layout of the level buffers 0..m-2.
   auto layout = [&](u32 cap) {
     u32 w = 0;
@@ -893,11 +938,14 @@ Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
 // Stratification (Tarjan, dependencies first)
 // ===========================================================================
 
-std::vector<std::vector<u32>> strata(Engine* e) {
-  const u32 n = (u32)e->rels.size();
+// Strongly connected components of the dependency graph (head -> every body
+// and negated relation), dependencies first.
+std::vector<std::vector<u32>> strata_of(u32 n, const std::vector<Rule>& rules) {
   std::vector<std::vector<u32>> dep(n);
-  for (auto& r : e->rules)
+  for (auto& r : rules) {
     for (auto& a : r.body) dep[r.head.rel].push_back(a.rel);
+    for (auto& a : r.negs) dep[r.head.rel].push_back(a.rel);
+  }
   std::vector<int> idx(n, -1), low(n, 0);
   std::vector<bool> on(n, false);
   std::vector<u32> st;
@@ -931,6 +979,22 @@ std::vector<std::vector<u32>> strata(Engine* e) {
   for (u32 v = 0; v < n; ++v)
     if (idx[v] < 0) go(v);
   return out;
+}
+
+std::vector<std::vector<u32>> strata(Engine* e) { return strata_of((u32)e->rels.size(), e->rules); }
+
+// Stratified negation: no rule may negate a relation of its own head's
+// component (the negated relation must be complete before the rule runs).
+void check_stratified(u32 nrels, const std::vector<Rule>& rules) {
+  std::vector<u32> comp(nrels, 0);
+  const auto sc = strata_of(nrels, rules);
+  for (u32 c = 0; c < sc.size(); ++c)
+    for (u32 rel : sc[c]) comp[rel] = c;
+  for (auto& r : rules)
+    for (auto& a : r.negs)
+      if (comp[a.rel] == comp[r.head.rel])
+        throw Error(WCDL_E_UNSUPPORTED, "program not stratifiable: a rule negates a relation "
+                                        "that depends on its head");
 }
 
 // ===========================================================================
@@ -1179,6 +1243,14 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
       if (cc.n >= 0xffffffffull) throw Error(WCDL_E_UNSUPPORTED, "join source exceeds 2^32-1 rows");
       P.atom_n[ai] = (u32)cc.n;
       for (size_t p = 0; p < u.order.size(); ++p) P.atom_col[ai][p] = cc.col[p].get();
+    }
+    // Negated atoms read complete relations of lower strata.
+    for (size_t k = 0; k < v.negs.size() && !R.skip; ++k) {
+      const AtomUse& u = v.negs[k];
+      Cols& cc = get_cols(e, u.rel, false, u.order);
+      if (cc.n >= 0xffffffffull) throw Error(WCDL_E_UNSUPPORTED, "negated relation exceeds 2^32-1 rows");
+      P.neg[k].n = (u32)cc.n;
+      for (size_t j = 0; j < u.order.size(); ++j) P.neg[k].col[j] = cc.n ? cc.col[j].get() : nullptr;
     }
     for (u32 L = 0; L < P.m && !R.skip; ++L)
       for (u32 s2 = 0; s2 < P.lvl[L].nsrc; ++s2) {
@@ -1936,6 +2008,7 @@ void batch_rewrite(Rule& r) {
   const u32 inst = r.nvars++;
   r.head.t.insert(r.head.t.begin(), Term{true, inst});
   for (auto& a : r.body) a.t.insert(a.t.begin(), Term{true, inst});
+  for (auto& a : r.negs) a.t.insert(a.t.begin(), Term{true, inst});
   if (!r.var_order.empty()) r.var_order.insert(r.var_order.begin(), inst);
 }
 
@@ -1956,6 +2029,13 @@ void validate_rule(Engine* e, const Rule& r) {
     check_atom(a);
     for (auto& t : a.t)
       if (t.var) bound[t.v] = true;
+  }
+  if (r.negs.size() > (size_t)MAXNEG) throw Error(WCDL_E_UNSUPPORTED, "more than 4 negated atoms");
+  for (auto& a : r.negs) {
+    check_atom(a);
+    for (auto& t : a.t)
+      if (t.var && !bound[t.v])
+        throw Error(WCDL_E_UNSAFE_RULE, "negated-atom variable not bound by a positive body atom");
   }
   for (auto& t : r.head.t)
     if (t.var && !bound[t.v]) throw Error(WCDL_E_UNSAFE_RULE, "head variable not bound by the body");
@@ -2015,6 +2095,8 @@ Rule from_c(const wcdl_rule* cr) {
     }
     r.cmps.push_back(x);
   }
+  if (cr->n_neg && !cr->neg) throw Error(WCDL_E_INVALID, "null negated atoms");
+  for (u32 i = 0; i < cr->n_neg; ++i) r.negs.push_back(atom(cr->neg[i]));
   r.nvars = nv;
   if (cr->var_order) r.var_order.assign(cr->var_order, cr->var_order + cr->n_vars);
   return r;
@@ -2075,6 +2157,18 @@ void parse_rules(Engine* e, const std::string& text, std::vector<Rule>& rules,
     }
     if (!lx.lit(":-")) lx.fail("expected ':-' or '.'");
     for (;;) {
+      if (lx.peek("!") && !lx.peek("!=")) {
+        // A negated atom  !name(...)
+        lx.lit("!");
+        std::string nid;
+        if (!lx.ident(nid) || !lx.peek("(")) lx.fail("expected an atom after '!'");
+        Atom a;
+        atom_args(a, nid);
+        r.negs.push_back(a);
+        if (lx.lit(".")) break;
+        if (!lx.lit(",")) lx.fail("expected ',' or '.'");
+        continue;
+      }
       size_t save = lx.i;
       std::string id;
       bool is_atom = lx.ident(id) && lx.peek("(");
@@ -2432,8 +2526,14 @@ wcdl_status wcdl_add_rule(wcdl_engine* e, const wcdl_rule* rule, uint32_t* rule_
     for (auto& a : r.body)
       if (a.rel < e->rels.size() && a.t.size() != e->rels[a.rel].user_arity)
         throw Error(WCDL_E_ARITY, "atom arity differs from the declaration");
+    for (auto& a : r.negs)
+      if (a.rel < e->rels.size() && a.t.size() != e->rels[a.rel].user_arity)
+        throw Error(WCDL_E_ARITY, "negated atom arity differs from the declaration");
     if (batched(e)) batch_rewrite(r);
     validate_rule(e, r);
+    std::vector<Rule> all = e->rules;
+    all.push_back(r);
+    check_stratified((u32)e->rels.size(), all);
     e->rules.push_back(r);
     if (rule_id) *rule_id = (u32)e->rules.size() - 1;
   });
@@ -2445,6 +2545,9 @@ wcdl_status wcdl_add_rules_text(wcdl_engine* e, const char* text) {
     std::vector<Rule> rules;
     std::vector<std::pair<u32, std::vector<u32>>> facts;
     parse_rules(e, text, rules, facts);
+    std::vector<Rule> all = e->rules;
+    all.insert(all.end(), rules.begin(), rules.end());
+    check_stratified((u32)e->rels.size(), all);
     for (auto& r : rules) e->rules.push_back(r);
     // Ground facts: group by relation and load.
     std::map<u32, std::vector<std::vector<u32>>> by_rel;
@@ -2506,6 +2609,9 @@ wcdl_status wcdl_split_rule(wcdl_engine* e, uint32_t rule_id, const uint32_t* at
           if (t.var) outer.insert(t.v);
     for (auto& t : r.head.t)
       if (t.var) outer.insert(t.v);
+    for (auto& a : r.negs)
+      for (auto& t : a.t)
+        if (t.var) outer.insert(t.v);
     std::vector<Cmp> helper_cmps, rest_cmps;
     for (auto& c : r.cmps) {
       bool in_a = !c.a.var || inner.count(c.a.v), in_b = !c.b.var || inner.count(c.b.v);
@@ -2581,6 +2687,7 @@ wcdl_status wcdl_split_rule(wcdl_engine* e, uint32_t rule_id, const uint32_t* at
       }
     consumer.body.push_back(helper.head);
     consumer.cmps = rest_cmps;
+    consumer.negs = r.negs;
     if (!reuse) declare(e, hname, (u32)shared.size(), true);
     try {
       if (!reuse) validate_rule(e, helper);
@@ -2714,6 +2821,10 @@ wcdl_status wcdl_autotune(wcdl_engine* e, const uint32_t* wg_per_cu, uint32_t n,
 wcdl_status wcdl_serve_begin(wcdl_engine* e) {
   return guarded(e, [&] {
     if (!batched(e)) throw Error(WCDL_E_STATE, "serving needs a batched engine");
+    for (auto& r : e->rules)
+      if (!r.negs.empty())
+        throw Error(WCDL_E_UNSUPPORTED, "a program with negation cannot be served (its single "
+                                        "semi-naive loop needs a positive program)");
     for (auto& R : e->rels) {
       R.full = copy_cols(e, R.base);
       R.full_ord.clear();

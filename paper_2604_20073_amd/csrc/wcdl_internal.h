@@ -23,6 +23,7 @@ constexpr int MAXV = WCDL_MAX_VARS;   // variables (join levels) per rule
 constexpr int MAXS = MAXN;            // sources per level (one per atom at most)
 constexpr int MAXB = 8;               // value bounds per level
 constexpr int MAXF = 4;               // inequality filters per level
+constexpr int MAXNEG = WCDL_MAX_NEG;  // negated atoms per rule
 constexpr u32 NONE = 0xffffffffu;
 
 // ---------------------------------------------------------------------------
@@ -166,11 +167,24 @@ struct DBound {       // x_level >= opnd + adj (lo) or x_level <= opnd - adj (hi
   DOperand o;
 };
 
+// A negated atom (stratified negation): a filter over a relation of a lower
+// stratum, tested at the level that binds its last variable.  Its sorted copy
+// holds its columns in `col` in search order (constants first, then
+// variables by level); a binding survives if no row equals the operands.
+struct DNeg {
+  const u32* col[MAXA];
+  DOperand val[MAXA];
+  u32 ncols;
+  u32 n;                  // rows of the copy
+  u32 level;              // level at which every variable of the atom is bound
+  u32 pad_;
+};
+
 struct DLevel {
   u32 nsrc;
   u32 nbnd;
   u32 nne;
-  u32 pad_;
+  u32 nneg;               // negated atoms tested at this level
   DSource src[MAXS];
   DBound bnd[MAXB];
   DOperand ne[MAXF];      // x_level != operand
@@ -198,6 +212,8 @@ struct DPlan {
   u64* stage_next;        // chunks handed out so far
   u64* chunk_tag;
   u32* ovf;               // per workgroup: 1 if its rows did not all fit
+  DNeg neg[MAXNEG];       // negated atoms, ordered by level
+  u32 nneg;
   u32 atom_n[MAXN];       // rows in each atom's sorted copy
   u32 atom_nconst[MAXN];  // leading constant columns of each atom
   u32 atom_const[MAXN][MAXA];

@@ -169,6 +169,20 @@ __device__ inline u32 operand(const Bufs& B, const DOperand& o, int L, u32 i, u3
   return B.val(L - 1, o.v, i);
 }
 
+// Stratified negation: true if no row of the negated atom's relation equals
+// its operands under the current binding (level L bound to v).  The copy is
+// sorted in the atom's search order, so each bound column narrows a range.
+__device__ inline bool neg_absent(const DNeg& ng, const Bufs& B, int L, u32 i, u32 v) {
+  u32 lo = 0, hi = ng.n;
+  for (u32 j = 0; j < ng.ncols; ++j) {
+    const u32 x = operand(B, ng.val[j], L, i, v);
+    const u32 l2 = lower_bound_u32(ng.col[j], lo, hi, x);
+    hi = upper_bound_u32(ng.col[j], l2, hi, x);
+    lo = l2;
+  }
+  return lo >= hi;
+}
+
 // Column of source s of a level (s varies per lane; the level does not).
 // The pointers are read as wave-uniform values and selected in registers; a
 // per-lane indexed read of the plan would put a dependent memory access in
@@ -297,6 +311,10 @@ __device__ inline bool try_candidate(const DPlan* P, const Bufs& B, int L, u32 i
       shi.put(s, hi);
     }
   }
+  // Negated atoms whose last variable is bound here.
+  if (ok && lv.nneg)
+    for (u32 k = 0; k < P->nneg; ++k)
+      if (P->neg[k].level == (u32)L) ok &= neg_absent(P->neg[k], B, L, i, v) ? 1u : 0u;
   return ok != 0;
 }
 
@@ -710,6 +728,16 @@ __device__ inline void leaf_probe(const DPlan* P, const Bufs& B, int L, int bl, 
     for (int k = 0; k < K; ++k) {
       const u32 found = hasb[k] ? fb[k] : (len[k] != 0 ? 1u : 0u) & (xb[k] == v[k] ? 1u : 0u);
       alive[k] &= (act[k] ^ 1u) | found;
+    }
+  }
+  // Negated atoms tested at the leaf.
+  if (uni(lv.nneg)) {
+    const u32 nneg = uni(P->nneg);
+    for (u32 n = 0; n < nneg; ++n) {
+      if (uni(P->neg[n].level) != (u32)L) continue;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (alive[k]) alive[k] &= neg_absent(P->neg[n], B, L, it[k], v[k]) ? 1u : 0u;
     }
   }
 }

@@ -85,7 +85,8 @@ class _Cmp(ctypes.Structure):
 class _Rule(ctypes.Structure):
     _fields_ = [("head", _Atom), ("n_body", ctypes.c_uint32), ("body", ctypes.POINTER(_Atom)),
                 ("n_cmp", ctypes.c_uint32), ("cmp", ctypes.POINTER(_Cmp)),
-                ("n_vars", ctypes.c_uint32), ("var_order", ctypes.POINTER(ctypes.c_uint32))]
+                ("n_vars", ctypes.c_uint32), ("var_order", ctypes.POINTER(ctypes.c_uint32)),
+                ("n_neg", ctypes.c_uint32), ("neg", ctypes.POINTER(_Atom))]
 
 
 _CMP_OPS = {"<": 0, "<=": 1, "!=": 2, ">": 3, ">=": 4}
@@ -279,11 +280,12 @@ class Engine:
     def add_rules(self, text: str):
         self._check(self._lib.wcdl_add_rules_text(self._e, text.encode()))
 
-    def add_rule(self, head, body, cmps=(), var_order=None) -> int:
-        """Register one rule given as data (wcdl_add_rule): head and body
-        atoms are (relation name, terms); a term is a variable name (str) or
-        a constant (int); cmps are (op, a, b) with op in < <= != > >=;
-        var_order lists every body variable once (None: planner's choice)."""
+    def add_rule(self, head, body, cmps=(), var_order=None, negs=()) -> int:
+        """Register one rule given as data (wcdl_add_rule): head, body and
+        negated atoms are (relation name, terms); a term is a variable name
+        (str) or a constant (int); cmps are (op, a, b) with op in < <= != >
+        >=; var_order lists every body variable once (None: planner's
+        choice)."""
         names = {}
 
         def term(t):
@@ -302,7 +304,8 @@ class Engine:
         h = atom(head)
         b = (_Atom * len(body))(*[atom(a) for a in body])
         c = (_Cmp * max(len(cmps), 1))(*[_Cmp(_CMP_OPS[op], term(x), term(y)) for op, x, y in cmps])
-        r = _Rule(h, len(body), b, len(cmps), c, 0, None)
+        ng = (_Atom * max(len(negs), 1))(*[atom(a) for a in negs])
+        r = _Rule(h, len(body), b, len(cmps), c, 0, None, len(negs), ng)
         if var_order is not None:
             vo = (ctypes.c_uint32 * len(var_order))(*[names[v] for v in var_order])
             keep.append(vo)
