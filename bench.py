@@ -230,9 +230,8 @@ def bench_batch(args):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1000.0 / args.steps
     log(f"batched: {len(batches)} sub-batches, {ms:.1f} ms, {derived} rows")
-    # Plain engine, one instance at a time, on a random sample; results of the
-    # sample are compared with the batched engine's (last sub-batch resident
-    # only, so re-run the sample's sub-batches for the comparison).
+    # Plain engine, one instance at a time, on a random sample (throughput
+    # reference).
     g = W.rng(cseed + 1)
     sample = sorted(g.choice(args.instances, size=min(args.plain_sample, args.instances),
                              replace=False).tolist())
@@ -241,7 +240,6 @@ def bench_batch(args):
         p.declare(n, k)
     p.add_rules(rules)
     plain_rows = 0
-    plain_res = {}
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for i in sample:
@@ -249,21 +247,33 @@ def bench_batch(args):
         p.load("edge", graphs[i])
         st = p.run()
         plain_rows += st["derived_rows"]
-        plain_res[i] = (p.size("path"), p.size("tri"))
     torch.cuda.synchronize()
     plain_ms = (time.perf_counter() - t1) * 1000.0
-    mism = 0
+    # Row check against the oracle: the largest instance and a random sample,
+    # read back from the batched engine (their sub-batches run again).
+    import oracle
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    check = sorted(set(W.rng(cseed + 2).choice(args.instances, size=min(8, args.instances),
+                                               replace=False).tolist())
+                   | {int(np.argmax(sizes))})
     where = {i: bi for bi, b in enumerate(batches) for i in b}
-    checked = 0
-    for bi in sorted({where[i] for i in sample})[:4]:
+    mism, checked, checked_rows = 0, 0, 0
+    for bi in sorted({where[i] for i in check}):
         e.clear("edge")
         e.load("edge", dev[bi])
         e.run()
-        for i in sample:
-            if where[i] == bi:
-                checked += 1
-                if (len(e.read_instance("path", i)), len(e.read_instance("tri", i))) != plain_res[i]:
+        for i in check:
+            if where[i] != bi:
+                continue
+            _, expect = oracle.evaluate({"edge": 2, "path": 2, "tri": 3}, rules,
+                                        {"edge": graphs[i]}, threads=threads)
+            checked += 1
+            for n in ("path", "tri"):
+                got = e.read_instance(n, i)
+                checked_rows += len(got)
+                if not np.array_equal(got, expect[n]):
                     mism += 1
+    log(f"oracle row check: {checked} instances, {checked_rows} rows, {mism} mismatches")
     batched_rate = derived / (ms / 1000.0)
     plain_rate = plain_rows / (plain_ms / 1000.0)
     out = {"metric": "derived tuples/sec to fixpoint", "value": round(batched_rate, 1),
@@ -276,49 +286,122 @@ def bench_batch(args):
            "plain_one_at_a_time": {"instances": len(sample), "ms": round(plain_ms, 1),
                                    "derived": plain_rows, "tuples_per_s": round(plain_rate, 1)},
            "batched_over_plain": round(batched_rate / plain_rate, 2) if plain_rate else None,
-           "sample_instances_compared": checked, "sample_mismatches": mism}
+           "sample_parity": {"instances": checked, "rows": checked_rows,
+                             "largest_n": int(sizes.max()), "match": mism == 0}}
     print(json.dumps(out), flush=True)
     e.close()
     p.close()
+    if mism:
+        log("sampled instances differ from the oracle's rows")
+        sys.exit(1)
+
+
+def _serve_gen(job):
+    """Worker: draw one request's facts and save them as .npy files."""
+    from paper_2604_20073_amd import workloads as W
+    req, d = job
+    facts = W.serving_facts(req)
+    for name, rows in facts.items():
+        np.save(os.path.join(d, f"{req['id']}_{name}.npy"), rows)
+    return req["id"], list(facts)
+
+
+def serve_facts(trace, d, procs):
+    """Facts of every request, drawn in `procs` processes (forked before the
+    GPU is touched) into .npy files under d and mapped back read-only."""
+    import multiprocessing
+    meta = {}
+    with multiprocessing.get_context("fork").Pool(procs) as pool:
+        for k, (rid, names) in enumerate(pool.imap_unordered(_serve_gen, [(r, d) for r in trace],
+                                                             chunksize=2)):
+            meta[rid] = names
+            if (k + 1) % 200 == 0:
+                log(f"generated {k + 1} / {len(trace)} requests")
+    return {rid: {n: np.load(os.path.join(d, f"{rid}_{n}.npy"), mmap_mode="r") for n in names}
+            for rid, names in meta.items()}
 
 
 def bench_serve(args):
-    """Poisson stream of mixed requests (TC, triangles, 4-cycles, points-to),
-    served with continuous batching and replayed first come first served on
-    plain engines; p50/p99 latency (arrival -> fixpoint) for both."""
-    from paper_2604_20073_amd import workloads as W
-    from paper_2604_20073_amd.serve import Server, replay_plain
+    """Poisson stream of mixed requests (TC, triangles, 4-cycles, points-to;
+    m log-uniform in [1e3, m_max]; the first `warm` requests warm up and are
+    left out of the statistics), served with continuous batching under a
+    memory pool and a per-request cap, and replayed first come first served
+    on plain engines with the same cap; p50/p99 latency (arrival ->
+    fixpoint), completions, rejections, throughput for both.  Every request
+    completed by both gives the same result sizes; a sample of small
+    requests is checked row for row against the oracle."""
+    import shutil
+    import tempfile
 
-    trace = W.serving_trace(args.requests, args.rate, W.SEED_BASE + 4, 1e3, args.m_max)
-    log(f"generating {len(trace)} requests")
-    facts = {r["id"]: W.serving_facts(r) for r in trace}
-    warm = W.serving_trace(16, args.rate, W.SEED_BASE + 44, 1e3, 1e4)
-    warm_facts = {r["id"]: W.serving_facts(r) for r in warm}
-    srv = Server()
-    srv.run(warm, warm_facts)
-    srv.close()
-    srv = Server()
-    served = srv.run(trace, facts)
-    srv.close()
-    log(f"served: p50 {served['p50_s']:.3f} s p99 {served['p99_s']:.3f} s in {served['wall_s']:.1f} s")
-    replay_plain(warm, warm_facts)
-    plain = replay_plain(trace, facts)
-    log(f"plain: p50 {plain['p50_s']:.3f} s p99 {plain['p99_s']:.3f} s in {plain['wall_s']:.1f} s")
-    same = sum(served["sizes"][i] == plain["sizes"][i] for i in served["sizes"])
-    out = {"metric": "served p50/p99 latency vs plain engine", "value": round(served["p99_s"] * 1e3, 3),
+    import oracle
+    from paper_2604_20073_amd import workloads as W
+    from paper_2604_20073_amd.serve import OUTPUTS, PROGRAMS, Server, replay_plain
+
+    n = args.requests + args.warm
+    trace = W.serving_trace(n, args.rate, W.SEED_BASE + 4, 1e3, args.m_max)
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    d = tempfile.mkdtemp(prefix="wcdl_serve_", dir="/dev/shm" if os.path.isdir("/dev/shm") else None)
+    try:
+        log(f"generating {n} requests ({sum(r['m'] for r in trace)} input rows) on {procs} processes")
+        t_gen = time.perf_counter()
+        facts = serve_facts(trace, d, procs)
+        log(f"generated in {time.perf_counter() - t_gen:.1f} s")
+        g = W.rng(W.SEED_BASE + 45)
+        small = [r["id"] for r in trace if r["m"] <= 20_000 and r["id"] >= args.warm]
+        check = set(g.choice(small, size=min(24, len(small)), replace=False).tolist())
+        cap, pool = int(args.cap_gib * (1 << 30)), int(args.pool_gib * (1 << 30))
+        srv = Server(mem_budget_bytes=pool, instance_cap_bytes=cap, max_active=args.max_active)
+        served = srv.run(trace, facts, keep_ids=check)
+        srv.close()
+        keep = [i for i in served["latency_s"] if i >= args.warm]
+        lat = sorted(served["latency_s"][i] for i in keep)
+        log(f"served: {served['completed']} completed, {served['rejected']} rejected in "
+            f"{served['wall_s']:.1f} s")
+        plain = replay_plain(trace, facts, instance_cap_bytes=cap)
+        plat = sorted(plain["latency_s"][i] for i in plain["latency_s"] if i >= args.warm)
+        log(f"plain: {plain['completed']} completed, {plain['rejected']} rejected in "
+            f"{plain['wall_s']:.1f} s")
+        both = [i for i in served["sizes"] if i in plain["sizes"]]
+        same = sum(served["sizes"][i] == plain["sizes"][i] for i in both)
+        mism = 0
+        by = {r["id"]: r for r in trace}
+        for i in sorted(check):
+            if i not in served["rows"]:
+                continue
+            rels, rules = PROGRAMS[by[i]["kind"]]
+            _, expect = oracle.evaluate(rels, rules, {k: np.asarray(v) for k, v in facts[i].items()})
+            for o in OUTPUTS[by[i]["kind"]]:
+                mism += 0 if np.array_equal(served["rows"][i][o], expect[o]) else 1
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+
+    def pct(xs, q):
+        return round(float(np.percentile(xs, q)), 4) if xs else None
+
+    sw = served["wall_s"]
+    out = {"metric": "served p50/p99 latency vs plain engine", "value": round(pct(lat, 99) * 1e3, 3),
            "unit": "ms (p99)", "n_gpus": 1, "higher_is_better": False, "dtype": "u32",
            "data": "synthetic",
-           "config": {"workload": f"served: {len(trace)} requests, Poisson {args.rate}/s, "
-                                  f"m log-uniform [1e3, {args.m_max:.0e}], tc/tri/c4/pt",
-                      "derived": served["derived"]},
-           "served": {k: served[k] for k in ("p50_s", "p99_s", "completed", "req_per_s", "wall_s",
-                                              "steps", "derived")},
-           "plain_fifo": {k: plain[k] for k in ("p50_s", "p99_s", "completed", "req_per_s",
-                                                "wall_s", "derived")},
-           "served_tuples_per_s": round(served["derived"] / served["wall_s"], 1),
-           "plain_tuples_per_s": round(plain["derived"] / plain["wall_s"], 1),
-           "requests_same_sizes": same}
+           "config": {"workload": (f"served: {args.requests} requests after {args.warm} warm-up, "
+                                   f"Poisson {args.rate}/s, m log-uniform [1e3, {args.m_max:.0e}], "
+                                   "tc/tri/c4/pt on ER or R-MAT"),
+                      "pool_gib": args.pool_gib, "cap_gib": args.cap_gib},
+           "served": {"p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "completed": len(keep),
+                      "rejected": served["rejected"], "req_per_s": round(served["completed"] / sw, 2),
+                      "wall_s": round(sw, 2), "steps": served["steps"],
+                      "tuples_per_s": round(served["derived"] / sw, 1)},
+           "plain_fifo": {"p50_s": pct(plat, 50), "p99_s": pct(plat, 99), "completed": len(plat),
+                          "rejected": plain["rejected"],
+                          "req_per_s": round(plain["completed"] / plain["wall_s"], 2),
+                          "wall_s": round(plain["wall_s"], 2),
+                          "tuples_per_s": round(plain["derived"] / plain["wall_s"], 1)},
+           "offered_req_per_s": args.rate,
+           "requests_same_sizes": f"{same} of {len(both)} completed by both",
+           "oracle_rows_checked": {"requests": len(check), "mismatches": mism}}
     print(json.dumps(out), flush=True)
+    if mism or same != len(both):
+        log("served results differ")
+        sys.exit(1)
 
 
 def main():
@@ -340,9 +423,13 @@ def main():
                          "(Sec. 5) that the runs use by default (same results): rmat: factor "
                          "edge(w,x), edge(x,z), edge(w,z) of q into ascending triangles; "
                          "andersen: factor load(v,p), pt(p,q) and store(p,w), pt(p,q)")
-    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--warm", type=int, default=200, help="serve: warm-up requests ahead of the trace")
     ap.add_argument("--rate", type=float, default=200.0)
-    ap.add_argument("--m-max", type=float, default=1e5)
+    ap.add_argument("--m-max", type=float, default=1e7)
+    ap.add_argument("--pool-gib", type=float, default=200.0, help="serve: memory pool")
+    ap.add_argument("--cap-gib", type=float, default=16.0, help="serve: per-request cap")
+    ap.add_argument("--max-active", type=int, default=256)
     ap.add_argument("--workload", choices=["rmat", "andersen", "batch", "serve"], default="rmat",
                     help="rmat: the skewed cyclic-join configuration (default, the headline); "
                          "andersen: the recursive points-to configuration (1M variables, "

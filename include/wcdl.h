@@ -148,6 +148,14 @@ typedef struct {
                                 a rule version produced per work unit last time
                                 (0 = default 125).  Rows that do not fit are
                                 recomputed by the write pass. */
+  uint64_t instance_cap_bytes; /* serving (batched engines): 0 = none.  Else an
+                                instance whose rows counted by one step's count
+                                passes take more than this many bytes (rows x
+                                stored head arity x 4) is rejected before the
+                                step writes anything: its rows are dropped from
+                                every relation and it is listed by
+                                wcdl_serve_rejected (the per-request form of
+                                WCDL_E_BUDGET). */
   uint64_t chunk_bytes;      /* candidate rows of one head relation written at
                                 once (Alg. 1 Phase 3): larger outputs are written
                                 in ranges of workgroups, each range deduplicated
@@ -364,11 +372,17 @@ wcdl_status wcdl_autotune(wcdl_engine* e, const uint32_t* wg_per_cu, uint32_t n,
  * which facts arrive does not change any instance's least model). */
 
 typedef struct {
-  uint64_t candidate_rows;  /* rows counted by this step's count passes: the
-                               memory bound of the step (x arity x 4 bytes) */
+  uint64_t candidate_rows;  /* rows counted by this step's count passes */
   uint64_t new_rows;        /* rows new to the relations after this step */
   uint64_t resident_rows;   /* rows held by all relations after this step */
   double wall_ms;
+  uint64_t bound_bytes;     /* bytes of the rows this step's count passes
+                               counted (rows x head arity x 4): the memory
+                               bound of the step (Alg. 1 Phase 2) */
+  uint64_t resident_bytes;  /* bytes held by every stored copy of every
+                               relation after the step */
+  uint64_t rejected;        /* instances rejected by this step
+                               (wcdl_config.instance_cap_bytes) */
 } wcdl_step_stats;
 
 /* Start serving: relations keep their loaded facts, derived relations are
@@ -400,6 +414,10 @@ wcdl_status wcdl_serve_live_static(wcdl_engine* e, uint32_t* ids, uint64_t cap, 
 /* Drop every row of the listed instances from every relation (frees their
  * memory).  ids need not be sorted. */
 wcdl_status wcdl_serve_release(wcdl_engine* e, const uint32_t* ids, uint64_t n);
+
+/* Instances rejected since serving began (instance_cap_bytes), ascending;
+ * writes min(count, cap) ids, *count receives the total. */
+wcdl_status wcdl_serve_rejected(wcdl_engine* e, uint32_t* ids, uint64_t cap, uint64_t* count);
 
 /* Stop serving (relations keep their contents). */
 wcdl_status wcdl_serve_end(wcdl_engine* e);

@@ -328,6 +328,10 @@ struct wcdl_engine {
   std::map<uint32_t, wcdl::Cols> pending;
   // Instances (batched engines): ids handed out so far.
   uint32_t next_instance = 0;
+  // Serving: largest instance id admitted so far; instances rejected by the
+  // per-instance memory cap.
+  uint32_t max_instance = 0;
+  std::set<uint32_t> rejected;
 };
 
 // An instance of a batched engine's program: its rows carry `id` in the
@@ -1012,6 +1016,13 @@ struct Stats {
   u64 bound_bytes = 0;  // bytes of candidate rows counted by count passes
 };
 
+// Serving: instances whose count-pass rows exceed the per-instance cap.
+struct Rejected : Error {
+  std::vector<u32> ids;
+  explicit Rejected(std::vector<u32> v)
+      : Error(WCDL_E_BUDGET, "instances over the per-instance memory cap"), ids(std::move(v)) {}
+};
+
 // HIP events around one kernel launch on its stream; read after a sync.
 struct KernelTimer {
   hipEvent_t a = nullptr, b = nullptr;
@@ -1288,12 +1299,40 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
   WCDL_HIP(hipStreamSynchronize(e->streams[0]));
   st.phase[WCDL_PH_INDEX] += ms_since(t_index);
   auto t_hist = Clock::now();
+  // Serving with a per-instance cap: count passes add up each instance's
+  // row bytes (indexed by instance id).
+  const bool per_instance = e->serving && e->cfg.instance_cap_bytes;
+  const bool bounded = e->cfg.mem_budget_bytes != 0;
+  DBuf<u64> inst_bytes, bound_acc;
+  DBuf<u32> abort_flag;
+  const u64 inst_n = (u64)e->max_instance + 1;
+  if (per_instance) {
+    inst_bytes = DBuf<u64>(e->mem.get(), inst_n);
+    fill_u64(ctx(e), inst_bytes.get(), inst_n, 0);
+  }
+  if (bounded) {
+    bound_acc = DBuf<u64>(e->mem.get(), 1);
+    fill_u64(ctx(e), bound_acc.get(), 1, 0);
+  }
+  if (per_instance || bounded) {
+    abort_flag = DBuf<u32>(e->mem.get(), 1);
+    fill_u32(ctx(e), abort_flag.get(), 1, 0);
+  }
+  const u64 held0 = bounded ? resident_bytes(e) : 0;
+  WCDL_HIP(hipStreamSynchronize(e->streams[0]));
   // ---- Phase A: plan upload, constant narrowing, root-key flags.
   for (size_t i = 0; i < vs.size(); ++i) {
     VRun& R = runs[i];
     Version& v = vs[i];
     if (R.skip) continue;
     DPlan& P = v.plan;
+    P.inst_bytes = per_instance ? reinterpret_cast<unsigned long long*>(inst_bytes.get()) : nullptr;
+    P.inst_n = (u32)inst_n;
+    P.inst_cap = e->cfg.instance_cap_bytes;
+    P.row_bytes = P.head_arity * 4;
+    P.bound_acc = bounded ? reinterpret_cast<unsigned long long*>(bound_acc.get()) : nullptr;
+    P.bound_limit = bounded && e->cfg.mem_budget_bytes > held0 ? e->cfg.mem_budget_bytes - held0 : 0;
+    P.abort = (per_instance || bounded) ? abort_flag.get() : nullptr;
     for (u32 L = 0; L < P.m; ++L)
       for (u32 s = 0; s < P.lvl[L].nsrc; ++s)
         P.lvl[L].src[s].col = P.atom_col[P.lvl[L].src[s].atom][v.src_pos[L][s]];
@@ -1454,6 +1493,27 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     if (R.total == 0) R.skip = true;
   }
   st.phase[WCDL_PH_COUNT] += ms_since(t_count);
+  u32 aborted = 0;
+  if (per_instance || bounded)
+    WCDL_HIP(hipMemcpy(&aborted, abort_flag.get(), sizeof(u32), hipMemcpyDeviceToHost));
+  if (per_instance) {
+    std::vector<u64> hb(inst_n);
+    WCDL_HIP(hipMemcpy(hb.data(), inst_bytes.get(), inst_n * sizeof(u64), hipMemcpyDeviceToHost));
+    std::vector<u32> over;
+    for (u64 id = 0; id < inst_n; ++id)
+      if (hb[id] > e->cfg.instance_cap_bytes) over.push_back((u32)id);
+    if (!over.empty()) throw Rejected(std::move(over));
+  }
+  if (aborted)
+    throw Error(WCDL_E_BUDGET, "the round's count passes crossed the memory budget of " +
+                                   std::to_string(e->cfg.mem_budget_bytes) + " bytes beside " +
+                                   std::to_string(held0) + " bytes of relations (stopped early)");
+  // Recounts (finer partitions of chunked heads) are not accounted again.
+  for (auto& R : runs) {
+    R.v->plan.inst_bytes = nullptr;
+    R.v->plan.bound_acc = nullptr;
+    R.v->plan.abort = nullptr;
+  }
   // Memory bound of the round: the counted rows must fit beside the
   // relations within the budget, else nothing of this round is written.
   u64 need = 0;
@@ -2300,6 +2360,8 @@ std::string helper_key(const Rule& h) {
   return k;
 }
 
+void drop_instances(Engine* e, const std::vector<u32>& ids);
+
 // One serving round: admitted facts not yet known join the deltas of their
 // relations, then one semi-naive round of every rule version over them.
 void serve_round(Engine* e, Stats& st, wcdl_step_stats& s) {
@@ -2323,7 +2385,21 @@ void serve_round(Engine* e, Stats& st, wcdl_step_stats& s) {
     if (it != R.delta_ord.end() && it->second.n) any = true;
   }
   if (any) {
-    auto fresh = new_rows(e, e->serve_versions, st);
+    std::map<u32, Cols> fresh;
+    for (;;) {
+      try {
+        fresh = new_rows(e, e->serve_versions, st);
+        break;
+      } catch (const Rejected& r) {
+        // Over the per-instance cap: drop those instances, count them, and
+        // run the round again without them.
+        for (u32 id : r.ids) e->rejected.insert(id);
+        s.rejected += r.ids.size();
+        sync_all(e);
+        drop_instances(e, r.ids);
+        st.bound_bytes = 0;
+      }
+    }
     for (u32 rel = 0; rel < e->rels.size(); ++rel) {
       Relation& R = e->rels[rel];
       auto it = fresh.find(rel);
@@ -2337,6 +2413,8 @@ void serve_round(Engine* e, Stats& st, wcdl_step_stats& s) {
   }
   for (auto& R : e->rels) s.resident_rows += R.full.n;
   s.candidate_rows = st.candidates;
+  s.bound_bytes = st.bound_bytes;
+  s.resident_bytes = resident_bytes(e);
 }
 
 // Instance ids that still have work: rows in some delta or pending facts.
@@ -2836,9 +2914,16 @@ wcdl_status wcdl_serve_begin(wcdl_engine* e) {
     for (u32 ri = 0; ri < e->rules.size(); ++ri)
       for (u32 j = 0; j < e->rules[ri].body.size(); ++j) {
         e->serve_versions.push_back(plan_version(e, ri, (int)j, e->cfg.flags));
-        e->serve_versions.back().sorted_output = false;
+        Version& v = e->serve_versions.back();
+        v.sorted_output = false;
+        if (e->cfg.instance_cap_bytes) {
+          // Per-instance row accounting runs in the count kernel's emission.
+          v.plan.leaf_fast = 0;
+          v.plan.xprod = 0;
+        }
       }
     e->pending.clear();
+    e->rejected.clear();
     e->serving = true;
     sync_all(e);
   });
@@ -2863,6 +2948,10 @@ wcdl_status wcdl_serve_admit(wcdl_engine* e, uint32_t rel, const uint32_t* const
       dp.push_back(tmp.back().get());
     }
     Cols srt = sort_rows(e, 0, canonical(k), dp, n_rows, true);
+    // Rows are sorted by instance: the last one holds the largest id.
+    u32 top = 0;
+    WCDL_HIP(hipMemcpy(&top, srt.col[0].get() + (srt.n - 1), sizeof(u32), hipMemcpyDeviceToHost));
+    e->max_instance = std::max(e->max_instance, top);
     auto it = e->pending.find(rel);
     if (it == e->pending.end()) {
       e->pending.emplace(rel, std::move(srt));
@@ -2952,6 +3041,17 @@ wcdl_status wcdl_serve_release(wcdl_engine* e, const uint32_t* ids, uint64_t n) 
   });
 }
 
+wcdl_status wcdl_serve_rejected(wcdl_engine* e, uint32_t* ids, uint64_t cap, uint64_t* count) {
+  return guarded(e, [&] {
+    u64 i = 0;
+    for (u32 v : e->rejected) {
+      if (ids && i < cap) ids[i] = v;
+      ++i;
+    }
+    if (count) *count = e->rejected.size();
+  });
+}
+
 wcdl_status wcdl_serve_end(wcdl_engine* e) {
   return guarded(e, [&] {
     e->serving = false;
@@ -2991,6 +3091,7 @@ wcdl_status wcdl_instance_load(wcdl_instance* in, uint32_t rel, const uint32_t* 
       return;
     }
     Cols srt = sort_rows(e, 0, canonical(k), dp, n_rows, true);
+    e->max_instance = std::max(e->max_instance, in->id);
     auto it = e->pending.find(rel);
     if (it == e->pending.end()) {
       e->pending.emplace(rel, std::move(srt));

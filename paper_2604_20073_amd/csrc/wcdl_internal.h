@@ -212,6 +212,19 @@ struct DPlan {
   u64* stage_next;        // chunks handed out so far
   u64* chunk_tag;
   u32* ovf;               // per workgroup: 1 if its rows did not all fit
+  // Serving: bytes of rows counted per instance (indexed by the instance id,
+  // the value of level 0), inst_n entries; NULL when not counted.
+  unsigned long long* inst_bytes;
+  u32 inst_n;
+  u32 row_bytes;          // head arity x 4
+  u64 inst_cap;           // bytes an instance may count (inst_bytes set)
+  // Memory-bounded count passes: bytes counted by every version of the
+  // round so far (bound_acc, NULL when unbounded) against bound_limit.  When
+  // a bound is crossed the count kernels set *abort and every workgroup stops
+  // at its next step (the round is then refused, its counts discarded).
+  unsigned long long* bound_acc;
+  u64 bound_limit;
+  u32* abort;
   DNeg neg[MAXNEG];       // negated atoms, ordered by level
   u32 nneg;
   u32 atom_n[MAXN];       // rows in each atom's sorted copy

@@ -425,6 +425,7 @@ struct WgState {
   u32 rng0[2 * MAXN];
   u64 sh[WG / 64];
   u64 alloc;          // arena chunk just taken (broadcast to the workgroup)
+  u32 stop;           // a memory bound was crossed (broadcast)
 };
 
 // Output state of a workgroup, held in registers by every thread (all
@@ -482,6 +483,25 @@ __device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, Em
   u32 mine = 0;
 #pragma unroll
   for (int k = 0; k < K; ++k) mine += alive[k];
+  if (MODE != 1 && P->inst_bytes) {
+    // Per-instance memory bound (serving): the instance is the level-0 value.
+    const u32 n = uni(P->inst_n), rb = uni(P->row_bytes);
+    const u64 cap = uni(P->inst_cap);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const u32 id = L == 0 ? v[k] : B.val(L - 1, 0, i[k]);
+      if (alive[k] && id < n) {
+        const u64 was = atomicAdd(&P->inst_bytes[id], (unsigned long long)rb);
+        if (was + rb > cap) atomicOr(P->abort, 1u);
+      }
+    }
+  }
+  if (MODE != 1 && P->bound_acc && mine) {
+    // Memory bound of the round: stop counting once it is crossed.
+    const u64 add = (u64)mine * uni(P->row_bytes);
+    const u64 was = atomicAdd(P->bound_acc, (unsigned long long)add);
+    if (was + add > uni(P->bound_limit)) atomicOr(P->abort, 1u);
+  }
   if (MODE == 0) {
     my_count += mine;
     return;
@@ -780,6 +800,12 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
   int bl = -1;       // buffer being drained; -1 = root keys
 
   for (;;) {
+    if (MODE != 1 && P->abort) {
+      // A memory bound was crossed: stop (the round will be refused).
+      if (threadIdx.x == 0) st.stop = atomicOr(P->abort, 0u);  // coherent read
+      __syncthreads();
+      if (uni(st.stop)) break;
+    }
     bl = uni(bl);
     if (bl < 0) {
       if (uni(st.key_next) > klast) break;

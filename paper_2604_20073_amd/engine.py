@@ -52,7 +52,7 @@ class _Config(ctypes.Structure):
                 ("streams", ctypes.POINTER(ctypes.c_void_p)), ("alloc", _Allocator),
                 ("mem_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("wg_per_cu", ctypes.c_uint32), ("stage_pct", ctypes.c_uint32),
-                ("chunk_bytes", ctypes.c_uint64)]
+                ("instance_cap_bytes", ctypes.c_uint64), ("chunk_bytes", ctypes.c_uint64)]
 
 
 class _Stats(ctypes.Structure):
@@ -66,7 +66,9 @@ class _Stats(ctypes.Structure):
 
 class _StepStats(ctypes.Structure):
     _fields_ = [("candidate_rows", ctypes.c_uint64), ("new_rows", ctypes.c_uint64),
-                ("resident_rows", ctypes.c_uint64), ("wall_ms", ctypes.c_double)]
+                ("resident_rows", ctypes.c_uint64), ("wall_ms", ctypes.c_double),
+                ("bound_bytes", ctypes.c_uint64), ("resident_bytes", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64)]
 
 
 class _Term(ctypes.Structure):
@@ -110,7 +112,7 @@ EXPORTS = [
     "wcdl_serve_live", "wcdl_serve_release", "wcdl_serve_end",
     "wcdl_instance_create", "wcdl_instance_id", "wcdl_instance_load", "wcdl_instance_size",
     "wcdl_instance_read", "wcdl_instance_destroy", "wcdl_run_batch", "wcdl_step",
-    "wcdl_serve_live_static",
+    "wcdl_serve_live_static", "wcdl_serve_rejected",
 ]
 
 
@@ -159,6 +161,7 @@ def lib():
     L.wcdl_serve_step.argtypes = [P, ctypes.POINTER(_StepStats)]
     L.wcdl_serve_live.argtypes = [P, pu32, u64, pu64]
     L.wcdl_serve_live_static.argtypes = [P, pu32, u64, pu64]
+    L.wcdl_serve_rejected.argtypes = [P, pu32, u64, pu64]
     L.wcdl_serve_release.argtypes = [P, pu32, u64]
     L.wcdl_serve_end.argtypes = [P]
     L.wcdl_work_slice.argtypes = [u64, u64, u64, pu64, pu64]
@@ -199,7 +202,7 @@ class Engine:
 
     def __init__(self, device: int = 0, streams=None, flags: int = 0, mem_budget: int = 0,
                  wg_per_cu: int = 0, stage_pct: int = 0, torch_alloc: bool = True,
-                 batched: bool = False, chunk_bytes: int = 0):
+                 batched: bool = False, chunk_bytes: int = 0, instance_cap: int = 0):
         import torch  # device memory and streams come from PyTorch
 
         self._torch = torch
@@ -215,6 +218,7 @@ class Engine:
         cfg.wg_per_cu = wg_per_cu
         cfg.stage_pct = stage_pct
         cfg.chunk_bytes = chunk_bytes
+        cfg.instance_cap_bytes = instance_cap
         self._keep = []
         if torch_alloc:
             dev = torch.device("cuda", device)
@@ -396,13 +400,23 @@ class Engine:
         s = _StepStats()
         self._check(self._lib.wcdl_serve_step(self._e, ctypes.byref(s)))
         return {"candidate_rows": s.candidate_rows, "new_rows": s.new_rows,
-                "resident_rows": s.resident_rows, "wall_ms": s.wall_ms}
+                "resident_rows": s.resident_rows, "wall_ms": s.wall_ms,
+                "bound_bytes": s.bound_bytes, "resident_bytes": s.resident_bytes,
+                "rejected": s.rejected}
 
     def serve_live(self) -> list:
         cnt = ctypes.c_uint64()
         self._check(self._lib.wcdl_serve_live(self._e, None, 0, ctypes.byref(cnt)))
         buf = (ctypes.c_uint32 * max(cnt.value, 1))()
         self._check(self._lib.wcdl_serve_live(self._e, buf, cnt.value, ctypes.byref(cnt)))
+        return [int(buf[i]) for i in range(cnt.value)]
+
+    def serve_rejected(self) -> list:
+        """Instances rejected by the per-instance cap since serving began."""
+        cnt = ctypes.c_uint64()
+        self._check(self._lib.wcdl_serve_rejected(self._e, None, 0, ctypes.byref(cnt)))
+        buf = (ctypes.c_uint32 * max(cnt.value, 1))()
+        self._check(self._lib.wcdl_serve_rejected(self._e, buf, cnt.value, ctypes.byref(cnt)))
         return [int(buf[i]) for i in range(cnt.value)]
 
     def serve_live_static(self) -> list:

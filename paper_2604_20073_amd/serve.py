@@ -5,19 +5,26 @@ arrive over time.  One batched engine holds the union of their programs,
 each kind on its own relations, every request being one instance.  The loop:
 
   1. move arrived requests into the queue;
-  2. admit queued requests while the memory bound allows: resident rows plus
-     the last step's count-pass bound (the rows its count passes reserved),
-     plus an allowance for the input of every request admitted since that
-     step (this one included), must stay within the budget; at most
-     `max_active` requests run at once;
+  2. admit queued requests while the memory bound allows: the bytes the
+     engine reported after the last step (every stored copy of every
+     relation, plus the rows that step's count passes counted, each at its
+     relation's stored arity x 4 bytes), plus an allowance for the input of
+     every request admitted since that step (this one included; `growth`
+     times its input bytes), must stay within the pool; at most `max_active`
+     requests run at once;
   3. run one engine step (one semi-naive round for every live instance, all
-     in the same launches);
+     in the same launches).  The engine rejects an instance whose rows
+     counted in one step exceed the per-request cap before anything is
+     written (the per-request memory bound); if a step's count passes do not
+     fit the pool at all (WCDL_E_BUDGET), the request admitted last is
+     rejected and the step is run again;
   4. requests no longer live have reached their fixpoint: record completion,
      release their rows.
 
 Every evaluation step runs in the engine's kernels; this module only decides
 when to admit, step and release.  `replay_plain` serves the same trace first
-come first served, one request at a time, on plain engines.
+come first served, one request at a time, on plain engines with the same
+per-request cap.
 """
 
 from __future__ import annotations
@@ -27,7 +34,7 @@ import time
 
 import numpy as np
 
-from .engine import Engine
+from .engine import Engine, WcdlError
 
 PROGRAMS = {
     "tc": ({"edge_tc": 2, "path": 2},
@@ -53,34 +60,41 @@ def percentile(xs, q):
 
 class Server:
     def __init__(self, mem_budget_bytes: int = 64 << 30, max_active: int = 256, device: int = 0,
-                 row_bytes: int = 16):
-        self.e = Engine(device=device, batched=True)
+                 instance_cap_bytes: int = 16 << 30, growth: int = 8):
+        self.e = Engine(device=device, batched=True, mem_budget=mem_budget_bytes,
+                        instance_cap=instance_cap_bytes)
+        self.stored_arity = {}
         for rels, _ in PROGRAMS.values():
             for name, k in rels.items():
                 if name not in self.e.ids:
                     self.e.declare(name, k)
+                    self.stored_arity[name] = k + 1  # the instance column
         self.e.add_rules("\n".join(r for _, r in PROGRAMS.values()))
         self.e.serve_begin()
         self.budget = mem_budget_bytes
         self.max_active = max_active
-        self.row_bytes = row_bytes
+        self.growth = growth
 
     def close(self):
         self.e.serve_end()
         self.e.close()
 
-    def run(self, trace: list, facts: dict, keep_results: bool = False) -> dict:
+    def input_bytes(self, req_facts: dict) -> int:
+        return sum(len(r) * self.stored_arity[name] * 4 for name, r in req_facts.items())
+
+    def run(self, trace: list, facts: dict, keep_results: bool = False, keep_ids=()) -> dict:
         """Serve `trace` (sorted by arrival; facts[id] = {relation: rows}).
         Returns latencies (arrival -> fixpoint) and per-request output sizes
-        (and rows if keep_results)."""
+        (and rows: of every request if keep_results, else of those in
+        keep_ids), and the rejected requests."""
         e = self.e
         queue = collections.deque()
-        active = {}            # id -> admission time
+        active = {}            # id -> (request, admission time), in admission order
         done = {}
+        rejected = {}          # id -> "cap" (per-request bound) or "pool"
         sizes, rows = {}, {}
         nxt = 0
-        last_bound = 0
-        resident = 0
+        last_bytes = 0         # resident + counted bytes reported by the last step
         admitted_allow = 0     # allowances of requests admitted since the last step
         steps = 0
         t0 = time.perf_counter()
@@ -92,12 +106,11 @@ class Server:
             # Admission by the memory bound of the last count pass.
             while queue and len(active) < self.max_active:
                 req = queue[0]
-                in_rows = sum(len(v) for v in facts[req["id"]].values())
-                need = (resident + last_bound + admitted_allow + 8 * in_rows) * self.row_bytes
-                if active and need > self.budget:
+                allow = self.growth * self.input_bytes(facts[req["id"]])
+                if active and last_bytes + admitted_allow + allow > self.budget:
                     break
                 queue.popleft()
-                admitted_allow += 8 * in_rows
+                admitted_allow += allow
                 for name, r in facts[req["id"]].items():
                     inst = np.concatenate([np.full((len(r), 1), req["id"], np.uint32),
                                            r.astype(np.uint32)], axis=1)
@@ -107,11 +120,26 @@ class Server:
                 if nxt < len(trace):
                     time.sleep(max(0.0, min(0.01, trace[nxt]["arrival"] - now)))
                 continue
-            st = e.serve_step()
+            try:
+                st = e.serve_step()
+            except WcdlError as x:
+                if x.code != -8:
+                    raise
+                # The step's count passes do not fit the pool: reject the
+                # request admitted last and run the step again.
+                victim = next(reversed(active))
+                active.pop(victim)
+                rejected[victim] = "pool"
+                e.serve_release([victim])
+                continue
             steps += 1
-            last_bound = st["candidate_rows"]
-            resident = st["resident_rows"]
+            last_bytes = st["resident_bytes"] + st["bound_bytes"]
             admitted_allow = 0
+            if st["rejected"]:
+                for i in e.serve_rejected():
+                    if i in active:
+                        active.pop(i)
+                        rejected[i] = "cap"
             live = set(e.serve_live())
             t_done = time.perf_counter() - t0
             finished = [i for i in active if i not in live]
@@ -119,7 +147,7 @@ class Server:
                 req, _ = active.pop(i)
                 done[i] = t_done - req["arrival"]
                 sizes[i] = {o: e.range(o, i)[1] for o in OUTPUTS[req["kind"]]}
-                if keep_results:
+                if keep_results or i in keep_ids:
                     rows[i] = {o: e.read_instance(o, i) for o in OUTPUTS[req["kind"]]}
             if finished:
                 e.serve_release(finished)
@@ -128,20 +156,22 @@ class Server:
         return {"latency_s": done, "sizes": sizes, "rows": rows, "wall_s": wall, "steps": steps,
                 "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
                 "completed": len(done), "req_per_s": len(done) / wall if wall else None,
-                "derived": sum(sum(v.values()) for v in sizes.values())}
+                "derived": sum(sum(v.values()) for v in sizes.values()),
+                "rejected": len(rejected), "rejected_ids": rejected}
 
 
-def replay_plain(trace: list, facts: dict, device: int = 0) -> dict:
+def replay_plain(trace: list, facts: dict, device: int = 0, instance_cap_bytes: int = 16 << 30) -> dict:
     """The same trace, first come first served, one request at a time, each
-    on a plain engine running its kind's program."""
+    on a plain engine running its kind's program; a request whose run
+    exceeds the per-request cap (WCDL_E_BUDGET) is rejected."""
     engines = {}
     for kind, (rels, rules) in PROGRAMS.items():
-        e = Engine(device=device)
+        e = Engine(device=device, mem_budget=instance_cap_bytes)
         for name, k in rels.items():
             e.declare(name, k)
         e.add_rules(rules)
         engines[kind] = e
-    done, sizes = {}, {}
+    done, sizes, rejected = {}, {}, []
     t0 = time.perf_counter()
     for req in trace:
         now = time.perf_counter() - t0
@@ -152,7 +182,13 @@ def replay_plain(trace: list, facts: dict, device: int = 0) -> dict:
             e.clear(name)
         for name, r in facts[req["id"]].items():
             e.load(name, r)
-        e.run()
+        try:
+            e.run()
+        except WcdlError as x:
+            if x.code != -8:
+                raise
+            rejected.append(req["id"])
+            continue
         done[req["id"]] = time.perf_counter() - t0 - req["arrival"]
         sizes[req["id"]] = {o: e.size(o) for o in OUTPUTS[req["kind"]]}
     wall = time.perf_counter() - t0
@@ -162,4 +198,4 @@ def replay_plain(trace: list, facts: dict, device: int = 0) -> dict:
     return {"latency_s": done, "sizes": sizes, "wall_s": wall,
             "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99), "completed": len(done),
             "req_per_s": len(done) / wall if wall else None,
-            "derived": sum(sum(v.values()) for v in sizes.values())}
+            "derived": sum(sum(v.values()) for v in sizes.values()), "rejected": len(rejected)}

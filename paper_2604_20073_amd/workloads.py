@@ -213,7 +213,7 @@ def batch_instance(config_seed: int, i: int, n: int, out_degree: int = 4) -> np.
 KINDS = ("tc", "tri", "c4", "pt")
 
 
-def serving_trace(n: int, rate: float, seed: int, m_lo: float = 1e3, m_hi: float = 1e5) -> list:
+def serving_trace(n: int, rate: float, seed: int, m_lo: float = 1e3, m_hi: float = 1e7) -> list:
     """n requests with exponential inter-arrival gaps (mean 1/rate seconds),
     a kind uniform over KINDS, an input size m log-uniform in [m_lo, m_hi]
     and a graph model (ER or R-MAT) uniform.  Facts are drawn separately by
@@ -232,10 +232,9 @@ def serving_facts(req: dict) -> dict:
     """Input relations of one request.
     tc:  disjoint union of ceil(m/1024) components of 256 nodes and 1,024
          edges each (ER, or R-MAT scale 8), so the closure stays linear in m;
-    tri: one graph with m edges on m/16 nodes (ER, or R-MAT scale
-         ceil(log2(m/16)));
-    c4:  one ER graph with m edges on m/4 nodes (sparser, so closed 4-walks
-         stay near 64 m);
+    tri, c4: one graph with m edges on m/16 nodes (ER, or R-MAT scale
+         ceil(log2(m/16))); closed 4-walks grow fast with m, so the largest
+         4-cycle requests exceed a per-request memory cap;
     pt:  the module-structured points-to generator with ceil(m/3500)
          modules and counts m/7, 4m/7, m/7, m/7."""
     kind, m, seed = req["kind"], req["m"], req["seed"]
@@ -247,15 +246,13 @@ def serving_facts(req: dict) -> dict:
             gph = er_graph(256, 1024, s) if req["model"] == "er" else rmat_graph(8, 1024, s)
             parts.append(gph + np.uint32(256 * c))
         return {"edge_tc": np.concatenate(parts)}
-    if kind == "tri":
+    if kind in ("tri", "c4"):
+        rel = "edge_tri" if kind == "tri" else "edge_c4"
         n = max(16, m // 16)
         if req["model"] == "er":
-            return {"edge_tri": er_graph(n, min(m, n * (n - 1)), seed)}
+            return {rel: er_graph(n, min(m, n * (n - 1)), seed)}
         scale = max(4, int(np.ceil(np.log2(max(m / 16, 2)))))
-        return {"edge_tri": rmat_graph(scale, min(m, (1 << scale) * ((1 << scale) - 1) // 4), seed)}
-    if kind == "c4":
-        n = max(8, m // 4)
-        return {"edge_c4": er_graph(n, min(m, n * (n - 1)), seed)}
+        return {rel: rmat_graph(scale, min(m, (1 << scale) * ((1 << scale) - 1) // 4), seed)}
     mods = max(1, -(-m // 3500))
     rel = andersen(seed, n_modules=mods, n_address_of=max(1, m // 7), n_assign=max(1, 4 * m // 7),
                    n_load=max(1, m // 7), n_store=max(1, m // 7))

@@ -193,3 +193,61 @@ def test_checked_mode_keeps_results():
     e.run()
     assert np.array_equal(e.read_numpy("pt"), expect["pt"])
     e.close()
+
+
+def test_serving_rejects_an_instance_over_its_cap():
+    """Serving with a per-instance cap: an instance whose rows counted in one
+    step exceed the cap is rejected before the step writes anything (its
+    rows leave every relation, it is listed as rejected); every other
+    instance reaches its oracle least model in the same steps."""
+    from paper_2604_20073_amd.serve import PROGRAMS
+    rels, rules = PROGRAMS["tc"]
+    e = Engine(batched=True, instance_cap=4 << 20)
+    for n, k in rels.items():
+        e.declare(n, k)
+    e.add_rules(rules)
+    e.serve_begin()
+    small = {i: W.er_graph(60 + 9 * i, 150 + 30 * i, 900 + i) for i in range(6)}
+    big = 6
+    for i, g in list(small.items()) + [(big, W.complete_graph(300))]:
+        e.serve_admit("edge_tc", np.concatenate([np.full((len(g), 1), i, np.uint32), g], axis=1))
+    rejected = 0
+    for _ in range(200):
+        st = e.serve_step()
+        rejected += st["rejected"]
+        if not e.serve_live():
+            break
+    assert rejected == 1 and e.serve_rejected() == [big]
+    assert e.range("path", big)[1] == 0 and e.range("edge_tc", big)[1] == 0
+    for i, g in small.items():
+        _, expect = oracle.evaluate(rels, rules, {"edge_tc": g})
+        assert np.array_equal(e.read_instance("path", i), expect["path"]), i
+    e.serve_end()
+    e.close()
+
+
+def test_budget_stops_the_count_pass_early():
+    """A plain engine whose memory budget a single count pass would cross
+    many times over: the count kernels stop once the bound is crossed and the
+    run fails with E_BUDGET quickly, keeping the loaded facts; the engine
+    then runs a small input exactly."""
+    import time
+    e = Engine(mem_budget=64 << 20)
+    e.declare("edge", 2)
+    e.declare("c", 4)
+    e.add_rules("c(w,x,y,z) :- edge(w,x), edge(x,y), edge(y,z), edge(z,w).")
+    e.load("edge", W.complete_graph(700))   # 700^4 / ... ~ 2.4e11 closed 4-walks
+    t = time.perf_counter()
+    with pytest.raises(WcdlError) as ei:
+        e.run()
+    assert ei.value.code == -8
+    assert time.perf_counter() - t < 30
+    e.clear("edge")
+    small = W.er_graph(60, 300, 901)
+    e.load("edge", small)
+    e.run()
+    _, expect = oracle.evaluate({"edge": 2, "c": 4},
+                                "c(w,x,y,z) :- edge(w,x), edge(x,y), edge(y,z), edge(z,w).",
+                                {"edge": small})
+    assert np.array_equal(e.read_numpy("c"), expect["c"])
+    e.close()

@@ -321,16 +321,35 @@ def test_staged_count_pass(stage_pct):
     e.close()
 
 
-def test_andersen_full_size_by_module():
+_MODULE_PT = {}  # module -> the oracle's least model of its inputs (shared by both runs)
+
+
+@pytest.mark.parametrize("split", [True, False], ids=["split", "as_written"])
+def test_andersen_full_size_by_module(split):
     """The full-size points-to configuration (1M variables, 200k heap sites,
-    3.5M input tuples).  Every input tuple stays inside one module, so the
-    least model is the union of per-module least models: the oracle runs on
-    the inputs of a few sampled modules (spread over popularity ranks) and
-    must match the engine's result restricted to those modules exactly."""
+    3.5M input tuples), with the load and store rules split as the benchmark
+    runs them and as written.  Every input tuple stays inside one module, so
+    the least model is the union of per-module least models: the oracle runs
+    on the inputs of sampled modules -- the two most popular ones (the Zipf
+    head, saturated at 1,200 x 200 facts) and four spread over the
+    popularity ranks -- with the split program (pinned equal to the rules as
+    written), and must match the engine's result restricted to those
+    modules exactly."""
+    import os
+    from paper_2604_20073_amd.serve import PROGRAMS
     rel = W.andersen(W.SEED_BASE + 2)
     names = {"addressOf": 2, "assign": 2, "load": 2, "store": 2, "pt": 2}
-    e, got, stats = gpu_eval(names, ANDERSEN, rel)
-    pt = got["pt"]
+    e = Engine()
+    for n, k in names.items():
+        e.declare(n, k)
+    e.add_rules(ANDERSEN)
+    if split:
+        e.split_rule(2, [0, 1])
+        e.split_rule(3, [0, 1])
+    for n, rows in rel.items():
+        e.load(n, rows)
+    stats = e.run()
+    pt = e.read_numpy("pt")
     V, Hm, H0 = 1000, 200, 1000 * 1000
 
     def module(ids):  # variables [0, H0) in blocks of V, heap sites above in blocks of Hm
@@ -340,12 +359,17 @@ def test_andersen_full_size_by_module():
     assert np.all(module(pt[:, 0]) == module(pt[:, 1]))  # no cross-module tuple
     counts = np.bincount(module(rel["assign"][:, 0]), minlength=1000)
     ranked = np.argsort(-counts, kind="stable")
-    for k in [int(ranked[r]) for r in (150, 250, 400, 900)]:
-        sub = {n: rows[module(rows[:, 0]) == k] for n, rows in rel.items()}
-        _, expect = oracle.evaluate(names, ANDERSEN, sub)
+    srels, srules = PROGRAMS["pt"]
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    for r in (0, 1, 150, 250, 400, 900):
+        k = int(ranked[r])
+        if k not in _MODULE_PT:
+            sub = {n: rows[module(rows[:, 0]) == k] for n, rows in rel.items()}
+            _MODULE_PT[k] = oracle.evaluate(srels, srules, sub, threads=threads)[1]
+        expect = _MODULE_PT[k]
         mine = pt[module(pt[:, 0]) == k]
         assert len(expect["pt"]) > 0
-        assert np.array_equal(mine, expect["pt"]), k
+        assert np.array_equal(mine, expect["pt"]), (r, k)
     assert stats["rounds"] > 5
     e.close()
 
@@ -378,6 +402,36 @@ def test_batched_instances_match_alone():
             assert np.array_equal(got, expect[n]), (i, n)
             total += len(got)
     assert stats["derived_rows"] == total
+    e.close()
+
+
+def test_batched_config3_sample_with_the_largest_instance():
+    """Instances of the batched workload itself (4,096 seeded ER graphs, n
+    log-uniform in [50, 5000], 4 out-edges per node): the largest instance
+    (the closure of ~5,000 nodes, 2.4e7 rows) and a random sample run
+    together in one batched engine under their own instance ids; each one's
+    rows equal the oracle's."""
+    import os
+    cseed = W.SEED_BASE + 3
+    sizes = W.batch_sizes(4096, cseed)
+    g = W.rng(cseed + 7)
+    pick = sorted(set(g.choice(4096, size=12, replace=False).tolist()) | {int(np.argmax(sizes))})
+    graphs = {i: W.batch_instance(cseed, i, int(sizes[i])) for i in pick}
+    rules = TC + "\n" + TRI
+    e = Engine(batched=True)
+    for n, k in {"edge": 2, "path": 2, "tri": 3}.items():
+        e.declare(n, k)
+    e.add_rules(rules)
+    e.load("edge", np.concatenate([np.concatenate([np.full((len(gr), 1), i, np.uint32), gr], axis=1)
+                                   for i, gr in graphs.items()]).astype(np.uint32))
+    e.run()
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    for i, gr in graphs.items():
+        _, expect = oracle.evaluate({"edge": 2, "path": 2, "tri": 3}, rules, {"edge": gr},
+                                    threads=threads)
+        for n in ("path", "tri"):
+            assert np.array_equal(e.read_instance(n, i), expect[n]), (i, n)
+    assert e.range("path", int(np.argmax(sizes)))[1] > 20_000_000
     e.close()
 
 
@@ -421,7 +475,7 @@ def test_autotune_keeps_results():
 
 def test_served_results_equal_alone():
     from paper_2604_20073_amd.serve import OUTPUTS, PROGRAMS, Server
-    trace = W.serving_trace(24, 400.0, 4242, m_lo=200, m_hi=3000)
+    trace = W.serving_trace(24, 400.0, 4242, m_lo=100, m_hi=400)
     facts = {r["id"]: W.serving_facts(r) for r in trace}
     srv = Server(max_active=8)
     res = srv.run(trace, facts, keep_results=True)
