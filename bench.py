@@ -351,18 +351,34 @@ def bench_serve(args):
         check = set(g.choice(small, size=min(24, len(small)), replace=False).tolist())
         cap, pool = int(args.cap_gib * (1 << 30)), int(args.pool_gib * (1 << 30))
         srv = Server(mem_budget_bytes=pool, instance_cap_bytes=cap, max_active=args.max_active)
-        served = srv.run(trace, facts, keep_ids=check)
+        slog = None
+        if args.step_log:
+            fh = open(args.step_log, "w", buffering=1)
+
+            def slog(line):
+                fh.write(f"{time.perf_counter() - t_gen:9.2f} {line}\n")
+        empty = {"latency_s": {}, "sizes": {}, "rows": {}, "wall_s": 0.0, "steps": 0, "derived": 0,
+                 "completed": 0, "rejected": 0, "not_reached": 0}
+        served, plain = empty, dict(empty)
+        if "served" in args.legs:
+            served = srv.run(trace, facts, keep_ids=check, progress=log, step_log=slog)
+            log(f"served: {served['completed']} completed, {served['rejected']} rejected in "
+                f"{served['wall_s']:.1f} s")
         srv.close()
         keep = [i for i in served["latency_s"] if i >= args.warm]
         lat = sorted(served["latency_s"][i] for i in keep)
-        log(f"served: {served['completed']} completed, {served['rejected']} rejected in "
-            f"{served['wall_s']:.1f} s")
-        plain = replay_plain(trace, facts, instance_cap_bytes=cap)
+        if "plain" in args.legs:
+            plain = replay_plain(trace, facts, instance_cap_bytes=cap, progress=log,
+                                 deadline_s=args.plain_deadline)
+            log(f"plain: {plain['completed']} completed, {plain['rejected']} rejected, "
+                f"{plain['not_reached']} not reached in {plain['wall_s']:.1f} s")
         plat = sorted(plain["latency_s"][i] for i in plain["latency_s"] if i >= args.warm)
-        log(f"plain: {plain['completed']} completed, {plain['rejected']} rejected in "
-            f"{plain['wall_s']:.1f} s")
         both = [i for i in served["sizes"] if i in plain["sizes"]]
         same = sum(served["sizes"][i] == plain["sizes"][i] for i in both)
+        if args.sizes_out:
+            with open(args.sizes_out, "w") as fh:
+                json.dump({"served": {str(i): v for i, v in served["sizes"].items()},
+                           "plain": {str(i): v for i, v in plain["sizes"].items()}}, fh)
         mism = 0
         by = {r["id"]: r for r in trace}
         for i in sorted(check):
@@ -378,8 +394,13 @@ def bench_serve(args):
     def pct(xs, q):
         return round(float(np.percentile(xs, q)), 4) if xs else None
 
-    sw = served["wall_s"]
-    out = {"metric": "served p50/p99 latency vs plain engine", "value": round(pct(lat, 99) * 1e3, 3),
+    def per_s(x, wall):
+        return round(x / wall, 2) if wall else None
+
+    sw, pw = served["wall_s"], plain["wall_s"]
+    p99 = pct(lat, 99) if "served" in args.legs else pct(plat, 99)
+    out = {"metric": "served p50/p99 latency vs plain engine",
+           "value": round(p99 * 1e3, 3) if p99 is not None else None,
            "unit": "ms (p99)", "n_gpus": 1, "higher_is_better": False, "dtype": "u32",
            "data": "synthetic",
            "config": {"workload": (f"served: {args.requests} requests after {args.warm} warm-up, "
@@ -387,15 +408,16 @@ def bench_serve(args):
                                    "tc/tri/c4/pt on ER or R-MAT"),
                       "pool_gib": args.pool_gib, "cap_gib": args.cap_gib},
            "served": {"p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "completed": len(keep),
-                      "rejected": served["rejected"], "req_per_s": round(served["completed"] / sw, 2),
+                      "rejected": served["rejected"], "req_per_s": per_s(served["completed"], sw),
                       "wall_s": round(sw, 2), "steps": served["steps"],
-                      "tuples_per_s": round(served["derived"] / sw, 1)},
+                      "tuples_per_s": per_s(served["derived"], sw)},
            "plain_fifo": {"p50_s": pct(plat, 50), "p99_s": pct(plat, 99), "completed": len(plat),
                           "rejected": plain["rejected"],
-                          "req_per_s": round(plain["completed"] / plain["wall_s"], 2),
-                          "wall_s": round(plain["wall_s"], 2),
-                          "tuples_per_s": round(plain["derived"] / plain["wall_s"], 1)},
-           "offered_req_per_s": args.rate,
+                          "not_reached": plain["not_reached"],
+                          "req_per_s": per_s(plain["completed"], pw),
+                          "wall_s": round(pw, 2),
+                          "tuples_per_s": per_s(plain["derived"], pw)},
+           "offered_req_per_s": args.rate, "legs": args.legs,
            "requests_same_sizes": f"{same} of {len(both)} completed by both",
            "oracle_rows_checked": {"requests": len(check), "mismatches": mism}}
     print(json.dumps(out), flush=True)
@@ -430,6 +452,11 @@ def main():
     ap.add_argument("--pool-gib", type=float, default=200.0, help="serve: memory pool")
     ap.add_argument("--cap-gib", type=float, default=16.0, help="serve: per-request cap")
     ap.add_argument("--max-active", type=int, default=256)
+    ap.add_argument("--step-log", default="", help="serve: write a line per admission and step here")
+    ap.add_argument("--legs", default="served,plain", help="serve: which of served,plain to run")
+    ap.add_argument("--plain-deadline", type=float, default=0.0,
+                    help="serve: start no plain request after this many seconds (0: none)")
+    ap.add_argument("--sizes-out", default="", help="serve: write per-request result sizes here")
     ap.add_argument("--workload", choices=["rmat", "andersen", "batch", "serve"], default="rmat",
                     help="rmat: the skewed cyclic-join configuration (default, the headline); "
                          "andersen: the recursive points-to configuration (1M variables, "

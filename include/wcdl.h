@@ -383,6 +383,8 @@ typedef struct {
                                relation after the step */
   uint64_t rejected;        /* instances rejected by this step
                                (wcdl_config.instance_cap_bytes) */
+  double phase_ms[WCDL_N_PHASES]; /* time of the step by phase, indexed by
+                                    WCDL_PH_* as in wcdl_run_stats */
 } wcdl_step_stats;
 
 /* Start serving: relations keep their loaded facts, derived relations are

@@ -1314,7 +1314,7 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     bound_acc = DBuf<u64>(e->mem.get(), 1);
     fill_u64(ctx(e), bound_acc.get(), 1, 0);
   }
-  if (per_instance || bounded) {
+  if (bounded) {
     abort_flag = DBuf<u32>(e->mem.get(), 1);
     fill_u32(ctx(e), abort_flag.get(), 1, 0);
   }
@@ -1332,7 +1332,7 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     P.row_bytes = P.head_arity * 4;
     P.bound_acc = bounded ? reinterpret_cast<unsigned long long*>(bound_acc.get()) : nullptr;
     P.bound_limit = bounded && e->cfg.mem_budget_bytes > held0 ? e->cfg.mem_budget_bytes - held0 : 0;
-    P.abort = (per_instance || bounded) ? abort_flag.get() : nullptr;
+    P.abort = bounded ? abort_flag.get() : nullptr;
     for (u32 L = 0; L < P.m; ++L)
       for (u32 s = 0; s < P.lvl[L].nsrc; ++s)
         P.lvl[L].src[s].col = P.atom_col[P.lvl[L].src[s].atom][v.src_pos[L][s]];
@@ -1494,7 +1494,7 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
   }
   st.phase[WCDL_PH_COUNT] += ms_since(t_count);
   u32 aborted = 0;
-  if (per_instance || bounded)
+  if (bounded)
     WCDL_HIP(hipMemcpy(&aborted, abort_flag.get(), sizeof(u32), hipMemcpyDeviceToHost));
   if (per_instance) {
     std::vector<u64> hb(inst_n);
@@ -2917,8 +2917,8 @@ wcdl_status wcdl_serve_begin(wcdl_engine* e) {
         Version& v = e->serve_versions.back();
         v.sorted_output = false;
         if (e->cfg.instance_cap_bytes) {
-          // Per-instance row accounting runs in the count kernel's emission.
-          v.plan.leaf_fast = 0;
+          // Per-instance row accounting runs in the count kernel (the
+          // cross-product path has no count pass).
           v.plan.xprod = 0;
         }
       }
@@ -2971,6 +2971,7 @@ wcdl_status wcdl_serve_step(wcdl_engine* e, wcdl_step_stats* out) {
     wcdl_step_stats s{};
     serve_round(e, st, s);
     s.wall_ms = ms_since(t0);
+    for (int i = 0; i < WCDL_N_PHASES; ++i) s.phase_ms[i] = st.phase[i];
     if (out) *out = s;
   });
 }

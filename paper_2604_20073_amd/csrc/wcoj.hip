@@ -435,7 +435,48 @@ struct Emit {
   u64 covered = 0;    // staged rows for which arena chunks are held
   u64 chunk0 = 0, chunk1 = 0;  // arena chunks of even / odd 4096-row ranges
   u32 ovf = 0;        // staging arena exhausted for this workgroup
+  // Memory-bound accounting of count passes, per lane: bytes of rows found
+  // for instance acc_id (serving cap) and for the round (budget), added to
+  // the global counters once they pass ACC_FLUSH or the instance changes,
+  // and at the end of the pass.
+  u32 acc_id = 0;
+  u64 acc_inst = 0, acc_all = 0;
 };
+
+constexpr u64 ACC_FLUSH = 64u << 10;
+
+// An instance over its cap is not a reason to stop the pass: workgroups that
+// work for it alone stop (k_join polls its total), the rest finish, and the
+// host drops every instance over its cap and counts again.
+__device__ inline void flush_inst(const DPlan* P, Emit& em) {
+  if (!em.acc_inst) return;
+  atomicAdd(&P->inst_bytes[em.acc_id], (unsigned long long)em.acc_inst);
+  em.acc_inst = 0;
+}
+
+__device__ inline void flush_all(const DPlan* P, Emit& em) {
+  if (!em.acc_all) return;
+  const u64 was = atomicAdd(P->bound_acc, (unsigned long long)em.acc_all);
+  if (was + em.acc_all > uni(P->bound_limit)) atomicOr(P->abort, 1u);
+  em.acc_all = 0;
+}
+
+// Account `rows` output rows of instance `id` (the level-0 value; ignored
+// unless serving with a cap) against the per-instance and round bounds.
+__device__ inline void account(const DPlan* P, Emit& em, u32 id, u64 rows) {
+  if (!rows) return;
+  const u64 bytes = rows * uni(P->row_bytes);
+  if (P->inst_bytes && id < uni(P->inst_n)) {
+    if (id != em.acc_id) flush_inst(P, em);
+    em.acc_id = id;
+    em.acc_inst += bytes;
+    if (em.acc_inst >= ACC_FLUSH) flush_inst(P, em);
+  }
+  if (P->bound_acc) {
+    em.acc_all += bytes;
+    if (em.acc_all >= ACC_FLUSH) flush_all(P, em);
+  }
+}
 
 // Inclusive prefix of candidate counts of buffer b; sets total, resets cursor.
 __device__ void finalize_buffer(const DPlan* P, u32* sm, WgState& st, int b) {
@@ -485,22 +526,11 @@ __device__ inline void emit_chunk(const DPlan* P, const Bufs& B, WgState& st, Em
   for (int k = 0; k < K; ++k) mine += alive[k];
   if (MODE != 1 && P->inst_bytes) {
     // Per-instance memory bound (serving): the instance is the level-0 value.
-    const u32 n = uni(P->inst_n), rb = uni(P->row_bytes);
-    const u64 cap = uni(P->inst_cap);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const u32 id = L == 0 ? v[k] : B.val(L - 1, 0, i[k]);
-      if (alive[k] && id < n) {
-        const u64 was = atomicAdd(&P->inst_bytes[id], (unsigned long long)rb);
-        if (was + rb > cap) atomicOr(P->abort, 1u);
-      }
-    }
-  }
-  if (MODE != 1 && P->bound_acc && mine) {
-    // Memory bound of the round: stop counting once it is crossed.
-    const u64 add = (u64)mine * uni(P->row_bytes);
-    const u64 was = atomicAdd(P->bound_acc, (unsigned long long)add);
-    if (was + add > uni(P->bound_limit)) atomicOr(P->abort, 1u);
+    for (int k = 0; k < K; ++k)
+      if (alive[k]) account(P, em, L == 0 ? v[k] : B.val(L - 1, 0, i[k]), 1);
+  } else if (MODE != 1 && P->bound_acc) {
+    account(P, em, 0, mine);  // memory bound of the round
   }
   if (MODE == 0) {
     my_count += mine;
@@ -799,10 +829,21 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
   Emit em;
   int bl = -1;       // buffer being drained; -1 = root keys
 
+  // Serving with a cap: a workgroup whose units all lie under one root key
+  // works for one instance (the level-0 value) and stops once that
+  // instance's counted bytes pass its cap.
+  const u32 solo = MODE != 1 && P->inst_bytes && kfirst == klast ? ldg(rs.U + kfirst) : ~0u;
+  u32 polls = 0;
   for (;;) {
-    if (MODE != 1 && P->abort) {
-      // A memory bound was crossed: stop (the round will be refused).
-      if (threadIdx.x == 0) st.stop = atomicOr(P->abort, 0u);  // coherent read
+    if (MODE != 1 && (P->abort || solo != ~0u)) {
+      // A memory bound was crossed: stop (the round will be refused, or the
+      // instance dropped and the round counted again).
+      if (threadIdx.x == 0) {
+        u32 stop = P->abort ? atomicOr(P->abort, 0u) : 0u;  // coherent read
+        if (!stop && solo < P->inst_n && (++polls & 7u) == 0)
+          stop = atomicAdd(&P->inst_bytes[solo], 0ull) > P->inst_cap ? 1u : 0u;
+        st.stop = stop;
+      }
       __syncthreads();
       if (uni(st.stop)) break;
     }
@@ -868,6 +909,15 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
       // Leaf level: every surviving candidate is an output row.
       if (MODE == 0 && P->leaf_fast) {  // every candidate is a row: just add
         if (threadIdx.x == 0) my_count += st.total[bl] - st.cur[bl];
+        if (P->inst_bytes || P->bound_acc) {
+          // Each item's candidates left in [cur, total) count for its instance.
+          const u64 c0 = uni(st.cur[bl]), c1 = uni(st.total[bl]);
+          for (u32 it = threadIdx.x; it < nb; it += WG) {
+            const u64 lo = it ? pre[it - 1] : 0, hi = pre[it];
+            const u64 a = lo > c0 ? lo : c0, z = hi < c1 ? hi : c1;
+            if (z > a) account(P, em, B.val(bl, 0, it), z - a);
+          }
+        }
         __syncthreads();
         if (threadIdx.x == 0) st.cur[bl] = st.total[bl];
         __syncthreads();
@@ -916,6 +966,10 @@ __global__ __launch_bounds__(WG) void k_join(const DPlan* __restrict__ P, RootSp
     bl = L;
   }
 
+  if (MODE != 1) {
+    if (P->inst_bytes) flush_inst(P, em);
+    if (P->bound_acc) flush_all(P, em);
+  }
   if (MODE == 0) {
     u64 tot;
     block_excl_scan(my_count, st.sh, &tot);

@@ -68,7 +68,7 @@ class _StepStats(ctypes.Structure):
     _fields_ = [("candidate_rows", ctypes.c_uint64), ("new_rows", ctypes.c_uint64),
                 ("resident_rows", ctypes.c_uint64), ("wall_ms", ctypes.c_double),
                 ("bound_bytes", ctypes.c_uint64), ("resident_bytes", ctypes.c_uint64),
-                ("rejected", ctypes.c_uint64)]
+                ("rejected", ctypes.c_uint64), ("phase_ms", ctypes.c_double * 8)]
 
 
 class _Term(ctypes.Structure):
@@ -402,7 +402,7 @@ class Engine:
         return {"candidate_rows": s.candidate_rows, "new_rows": s.new_rows,
                 "resident_rows": s.resident_rows, "wall_ms": s.wall_ms,
                 "bound_bytes": s.bound_bytes, "resident_bytes": s.resident_bytes,
-                "rejected": s.rejected}
+                "rejected": s.rejected, "phase_ms": dict(zip(PHASES, list(s.phase_ms)))}
 
     def serve_live(self) -> list:
         cnt = ctypes.c_uint64()

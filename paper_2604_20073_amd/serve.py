@@ -82,11 +82,14 @@ class Server:
     def input_bytes(self, req_facts: dict) -> int:
         return sum(len(r) * self.stored_arity[name] * 4 for name, r in req_facts.items())
 
-    def run(self, trace: list, facts: dict, keep_results: bool = False, keep_ids=()) -> dict:
+    def run(self, trace: list, facts: dict, keep_results: bool = False, keep_ids=(),
+            progress=None, step_log=None) -> dict:
         """Serve `trace` (sorted by arrival; facts[id] = {relation: rows}).
         Returns latencies (arrival -> fixpoint) and per-request output sizes
         (and rows: of every request if keep_results, else of those in
-        keep_ids), and the rejected requests."""
+        keep_ids), and the rejected requests.  `progress` receives a line
+        every 10 s and for every slow step; `step_log`, if given, a line for
+        every admission and every step."""
         e = self.e
         queue = collections.deque()
         active = {}            # id -> (request, admission time), in admission order
@@ -98,8 +101,13 @@ class Server:
         admitted_allow = 0     # allowances of requests admitted since the last step
         steps = 0
         t0 = time.perf_counter()
+        t_note = 0.0
         while nxt < len(trace) or queue or active:
             now = time.perf_counter() - t0
+            if progress and now - t_note > 10.0:
+                t_note = now
+                progress(f"served {len(done)} done, {len(rejected)} rejected, {len(active)} active, "
+                         f"{len(queue)} queued at {now:.0f} s")
             while nxt < len(trace) and trace[nxt]["arrival"] <= now:
                 queue.append(trace[nxt])
                 nxt += 1
@@ -116,6 +124,12 @@ class Server:
                                            r.astype(np.uint32)], axis=1)
                     e.serve_admit(name, inst)
                 active[req["id"]] = (req, time.perf_counter() - t0)
+                if step_log:
+                    step_log(f"admit {req['id']} {req['kind']} m={req.get('m')} "
+                             f"active={len(active)}")
+                if progress and req.get("m", 0) >= 1_000_000:
+                    progress(f"admitted request {req['id']} ({req['kind']}, m={req['m']}) with "
+                             f"{len(active)} active")
             if not active:
                 if nxt < len(trace):
                     time.sleep(max(0.0, min(0.01, trace[nxt]["arrival"] - now)))
@@ -131,8 +145,21 @@ class Server:
                 active.pop(victim)
                 rejected[victim] = "pool"
                 e.serve_release([victim])
+                if progress:
+                    progress(f"step does not fit the pool: rejected request {victim}")
                 continue
             steps += 1
+            if step_log:
+                step_log(f"step {steps} {st['wall_ms']:.1f} ms active={len(active)} "
+                         f"cand={st['candidate_rows']} new={st['new_rows']} "
+                         f"resident={st['resident_bytes']} counted={st['bound_bytes']} "
+                         f"over_cap={st['rejected']} phases_ms=" +
+                         ",".join(f"{k}:{v:.1f}" for k, v in st.get("phase_ms", {}).items() if v))
+            if progress and st["wall_ms"] > 2000:
+                progress(f"step {steps}: {st['wall_ms'] / 1e3:.1f} s, {len(active)} active, "
+                         f"{st['candidate_rows']} candidates, {st['new_rows']} new rows, "
+                         f"resident {st['resident_bytes'] / 2**30:.1f} GiB, "
+                         f"counted {st['bound_bytes'] / 2**30:.1f} GiB, {st['rejected']} over the cap")
             last_bytes = st["resident_bytes"] + st["bound_bytes"]
             admitted_allow = 0
             if st["rejected"]:
@@ -160,10 +187,13 @@ class Server:
                 "rejected": len(rejected), "rejected_ids": rejected}
 
 
-def replay_plain(trace: list, facts: dict, device: int = 0, instance_cap_bytes: int = 16 << 30) -> dict:
+def replay_plain(trace: list, facts: dict, device: int = 0, instance_cap_bytes: int = 16 << 30,
+                 progress=None, deadline_s: float = 0.0) -> dict:
     """The same trace, first come first served, one request at a time, each
     on a plain engine running its kind's program; a request whose run
-    exceeds the per-request cap (WCDL_E_BUDGET) is rejected."""
+    exceeds the per-request cap (WCDL_E_BUDGET) is rejected.  With a
+    deadline, no request is started after it (those left are reported as
+    not reached)."""
     engines = {}
     for kind, (rels, rules) in PROGRAMS.items():
         e = Engine(device=device, mem_budget=instance_cap_bytes)
@@ -173,8 +203,16 @@ def replay_plain(trace: list, facts: dict, device: int = 0, instance_cap_bytes: 
         engines[kind] = e
     done, sizes, rejected = {}, {}, []
     t0 = time.perf_counter()
+    t_note = 0.0
+    reached = 0
     for req in trace:
         now = time.perf_counter() - t0
+        if deadline_s and now > deadline_s:
+            break
+        reached += 1
+        if progress and now - t_note > 10.0:
+            t_note = now
+            progress(f"plain {len(done)} done, {len(rejected)} rejected at {now:.0f} s")
         if req["arrival"] > now:
             time.sleep(req["arrival"] - now)
         e = engines[req["kind"]]
@@ -198,4 +236,5 @@ def replay_plain(trace: list, facts: dict, device: int = 0, instance_cap_bytes: 
     return {"latency_s": done, "sizes": sizes, "wall_s": wall,
             "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99), "completed": len(done),
             "req_per_s": len(done) / wall if wall else None,
-            "derived": sum(sum(v.values()) for v in sizes.values()), "rejected": len(rejected)}
+            "derived": sum(sum(v.values()) for v in sizes.values()), "rejected": len(rejected),
+            "not_reached": len(trace) - reached}
