@@ -173,6 +173,70 @@ def bench_andersen(args):
     e.close()
 
 
+SAME_GEN = ("sg(x,y) :- par(p,x), par(p,y), x != y.\n"
+            "sg(x,y) :- par(a,x), sg(a,b), par(b,y).")
+
+
+def bench_sg(args):
+    """Same generation (three body atoms in the recursive rule) on a
+    finite-element-shaped mesh, under the worst-case optimal plan and under
+    the binary-join plan (wcdl_binary_plan: the intermediate h(x,b) is
+    materialised every round); derived sg tuples per second for each, the
+    relations compared whole."""
+    import torch
+
+    from paper_2604_20073_amd import Engine
+    from paper_2604_20073_amd import workloads as W
+
+    par = W.mesh_graph(args.mesh_side, W.SEED_BASE + 6)
+    log(f"mesh {args.mesh_side} x {args.mesh_side}: {len(par)} edges")
+    dev = torch.from_numpy(par.view(np.int32)).cuda()
+    result = {}
+    rows = {}
+    for plan in ("wcoj", "binary"):
+        e = Engine(device=0, wg_per_cu=args.wg_per_cu, flags=args.flags)
+        e.declare("par", 2)
+        e.declare("sg", 2)
+        e.add_rules(SAME_GEN)
+        if plan == "binary":
+            e.binary_plan()
+        e.load("par", dev)
+        for i in range(args.warmup):
+            st = e.run()
+            log(f"{plan} warmup {i}: {st['wall_ms']:.1f} ms, rounds={st['rounds']}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = []
+        for i in range(args.steps):
+            stats.append(e.run())
+            log(f"{plan} step {i}: {stats[-1]['wall_ms']:.1f} ms")
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        n_sg = e.size("sg")
+        result[plan] = {"ms_per_step": round(ms, 3), "rounds": stats[0]["rounds"], "sg": n_sg,
+                        "candidate_rows": stats[0]["candidate_rows"],
+                        "intermediate_rows": sum(e.helper_sizes()),
+                        "phase_ms": {k: round(sum(x["phase_ms"][k] for x in stats) / args.steps, 2)
+                                     for k in stats[0]["phase_ms"]}}
+        rows[plan] = e.read_numpy("sg")
+        e.close()
+    same = bool(np.array_equal(rows["wcoj"], rows["binary"]))
+    w, b = result["wcoj"], result["binary"]
+    out = {"metric": "derived tuples/sec to fixpoint", "value": round(w["sg"] / (w["ms_per_step"] / 1e3), 1),
+           "unit": "tuples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": w["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": (f"same generation on a {args.mesh_side}x{args.mesh_side} grid "
+                                   f"mesh, {len(par)} directed edges"), "sg": w["sg"]},
+           "wcoj": w, "binary_join": b,
+           "speedup_vs_binary": round(b["ms_per_step"] / w["ms_per_step"], 3),
+           "same_relation": same}
+    print(json.dumps(out), flush=True)
+    if not same:
+        log("the two plans differ")
+        sys.exit(1)
+
+
 def bench_batch(args):
     """Many small instances: TC + triangles on seeded ER graphs, n log-uniform
     in [50, 5000], 4 out-edges per node.  All instances run in batched
@@ -449,7 +513,8 @@ def main():
     ap.add_argument("--warm", type=int, default=200, help="serve: warm-up requests ahead of the trace")
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--m-max", type=float, default=1e7)
-    ap.add_argument("--pool-gib", type=float, default=200.0, help="serve: memory pool")
+    ap.add_argument("--pool-gib", type=float, default=110.0,
+                    help="serve: memory pool (resident plus counted bytes; a step needs about as much again for sort scratch and merged copies)")
     ap.add_argument("--cap-gib", type=float, default=16.0, help="serve: per-request cap")
     ap.add_argument("--max-active", type=int, default=256)
     ap.add_argument("--step-log", default="", help="serve: write a line per admission and step here")
@@ -457,7 +522,8 @@ def main():
     ap.add_argument("--plain-deadline", type=float, default=0.0,
                     help="serve: start no plain request after this many seconds (0: none)")
     ap.add_argument("--sizes-out", default="", help="serve: write per-request result sizes here")
-    ap.add_argument("--workload", choices=["rmat", "andersen", "batch", "serve"], default="rmat",
+    ap.add_argument("--mesh-side", type=int, default=111, help="sg: grid side of the mesh")
+    ap.add_argument("--workload", choices=["rmat", "andersen", "batch", "serve", "sg"], default="rmat",
                     help="rmat: the skewed cyclic-join configuration (default, the headline); "
                          "andersen: the recursive points-to configuration (1M variables, "
                          "200k heap sites, 3.5M input tuples)")
@@ -497,6 +563,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "sg":
+        return bench_sg(args)
 
     log(f"generating R-MAT scale {args.scale}, {args.edges} edges")
     edges = W.rmat_graph(args.scale, args.edges, W.SEED_BASE + 1)

@@ -284,6 +284,19 @@ wcdl_status wcdl_rule_count(const wcdl_engine* e, uint32_t* n);
 wcdl_status wcdl_split_rule(wcdl_engine* e, uint32_t rule_id, const uint32_t* atom_idx,
                             uint32_t n, uint32_t* helper_rel);
 
+/* Binary-join plan, for comparison with the worst-case optimal plans (Sec.
+ * 7.2, Tab. 3: a conventional engine evaluates a body of three or more atoms
+ * as a chain of two-way joins and materialises each intermediate relation
+ * every iteration).  Every rule with three or more body atoms becomes a
+ * left-deep chain: atoms 0..k-2 are factored into a helper relation
+ * (wcdl_split_rule), whose own rule is split the same way until every body
+ * has at most two atoms.  The least model of every declared relation is
+ * unchanged; helpers hold the intermediate results as relations of their
+ * own.  Call before any wcdl_split_rule (else WCDL_E_STATE) and not while
+ * serving.  All or nothing: on error no rule changes.  *n_helpers (may be
+ * NULL) receives the number of helper relations made. */
+wcdl_status wcdl_binary_plan(wcdl_engine* e, uint32_t* n_helpers);
+
 /* ---- Evaluation ------------------------------------------------------- */
 
 /* Phase indices of wcdl_run_stats.phase_ms (device time, summed over rounds). */

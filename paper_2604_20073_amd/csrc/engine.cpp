@@ -2787,6 +2787,44 @@ wcdl_status wcdl_split_rule(wcdl_engine* e, uint32_t rule_id, const uint32_t* at
   });
 }
 
+wcdl_status wcdl_binary_plan(wcdl_engine* e, uint32_t* n_helpers) {
+  return guarded(e, [&] {
+    if (e->serving) throw Error(WCDL_E_STATE, "serving");
+    for (auto& r : e->rules)
+      if (!r.orig.empty()) throw Error(WCDL_E_STATE, "a rule is already split");
+    // All or nothing: on failure the rules and relations are put back.
+    const std::vector<Rule> rules0 = e->rules;
+    const size_t nrels0 = e->rels.size();
+    const uint32_t count0 = e->helper_count;
+    const auto keys0 = e->helper_keys;
+    u32 made = 0;
+    try {
+      // Rules appended by the splits (the helpers) are visited in turn.
+      for (u32 r = 0; r < e->rules.size(); ++r) {
+        const u32 k = (u32)e->rules[r].body.size();
+        if (k < 3 || !e->rules[r].orig.empty()) continue;
+        std::vector<u32> idx(k - 1);
+        for (u32 a = 0; a + 1 < k; ++a) idx[a] = a;
+        const size_t before = e->rules.size();
+        u32 h = 0;
+        const wcdl_status st = wcdl_split_rule(e, r, idx.data(), k - 1, &h);
+        if (st != WCDL_OK) throw Error(st, "binary plan of rule " + std::to_string(r) + ": " + e->err);
+        made += e->rules.size() > before ? 1u : 0u;
+      }
+    } catch (...) {
+      e->rules = rules0;
+      while (e->rels.size() > nrels0) {
+        e->rel_ids.erase(e->rels.back().name);
+        e->rels.pop_back();
+      }
+      e->helper_count = count0;
+      e->helper_keys = keys0;
+      throw;
+    }
+    if (n_helpers) *n_helpers = made;
+  });
+}
+
 wcdl_status wcdl_run(wcdl_engine* e, wcdl_run_stats* stats) {
   return guarded(e, [&] { run_program(e, stats); });
 }

@@ -105,7 +105,8 @@ _lib = None
 EXPORTS = [
     "wcdl_config_default", "wcdl_create", "wcdl_destroy", "wcdl_last_error",
     "wcdl_declare_relation", "wcdl_relation_id", "wcdl_load_columns", "wcdl_clear_relation",
-    "wcdl_add_rule", "wcdl_add_rules_text", "wcdl_rule_count", "wcdl_split_rule", "wcdl_run",
+    "wcdl_add_rule", "wcdl_add_rules_text", "wcdl_rule_count", "wcdl_split_rule",
+    "wcdl_binary_plan", "wcdl_run",
     "wcdl_relation_size", "wcdl_read_columns", "wcdl_delta_sizes", "wcdl_work_slice",
     "wcdl_owner_key", "wcdl_decode_unit", "wcdl_relation_range", "wcdl_read_rows",
     "wcdl_autotune", "wcdl_serve_begin", "wcdl_serve_admit", "wcdl_serve_step",
@@ -149,6 +150,7 @@ def lib():
     L.wcdl_step.argtypes = [P, ctypes.POINTER(P), u32, ctypes.POINTER(ctypes.c_uint8), pu64]
     L.wcdl_rule_count.argtypes = [P, pu32]
     L.wcdl_split_rule.argtypes = [P, u32, pu32, u32, pu32]
+    L.wcdl_binary_plan.argtypes = [P, pu32]
     L.wcdl_run.argtypes = [P, ctypes.POINTER(_Stats)]
     L.wcdl_relation_size.argtypes = [P, u32, pu64]
     L.wcdl_read_columns.argtypes = [P, u32, ctypes.POINTER(P), u64, pu64, ctypes.c_int]
@@ -344,6 +346,25 @@ class Engine:
         n = ctypes.c_uint32()
         self._check(self._lib.wcdl_rule_count(self._e, ctypes.byref(n)))
         return n.value
+
+    def binary_plan(self) -> int:
+        """Rewrite every rule of three or more body atoms into a left-deep
+        chain of two-atom joins through helper relations; returns the number
+        of helpers made."""
+        n = ctypes.c_uint32()
+        self._check(self._lib.wcdl_binary_plan(self._e, ctypes.byref(n)))
+        return n.value
+
+    def helper_sizes(self) -> list:
+        """Row counts of the relations made by splits (ids after the declared
+        ones), in order of creation."""
+        out, rid = [], len(self.ids)
+        while True:
+            n = ctypes.c_uint64()
+            if self._lib.wcdl_relation_size(self._e, rid, ctypes.byref(n)) != 0:
+                return out
+            out.append(n.value)
+            rid += 1
 
     def split_rule(self, rule_id: int, atoms) -> int:
         a = (ctypes.c_uint32 * len(atoms))(*atoms)

@@ -17,6 +17,8 @@ shapes):
 * ``rmat_graph``   -- R-MAT (a, b, c, d) quadrant recursion, hubs at low ids.
 * ``andersen``     -- module-structured points-to input relations.
 * ``batch_sizes``  -- log-uniform instance sizes for batched runs.
+* ``mesh_graph``   -- a 2-D grid mesh, both edge directions, permuted ids
+  (the finite-element meshes of the Same Generation benchmark, Tab. 3).
 * path / cycle / complete graphs for closed-form checks.
 """
 
@@ -121,6 +123,21 @@ def complete_graph(n: int) -> np.ndarray:
     return np.ascontiguousarray(np.stack([u[keep], v[keep]], axis=1))
 
 
+def mesh_graph(side: int, seed: int) -> np.ndarray:
+    """A side x side grid, each node joined to its 4 neighbours in both
+    directions (4 side (side - 1) edges), node ids a seeded permutation of
+    [0, side^2): the shape of a finite-element mesh (sparse, planar, large
+    diameter, so recursive rules over it run for many rounds)."""
+    g = rng(seed)
+    perm = g.permutation(side * side).astype(np.uint32)
+    ids = perm.reshape(side, side)
+    right = np.stack([ids[:, :-1].ravel(), ids[:, 1:].ravel()], axis=1)
+    down = np.stack([ids[:-1, :].ravel(), ids[1:, :].ravel()], axis=1)
+    one = np.concatenate([right, down])
+    both = np.concatenate([one, one[:, ::-1]])
+    return np.ascontiguousarray(both[g.permutation(len(both))])
+
+
 # ---------------------------------------------------------------------------
 # Program-analysis-shaped relations (Andersen points-to inputs).
 # ---------------------------------------------------------------------------
@@ -176,6 +193,118 @@ def andersen(seed: int, n_modules=1000, vars_per_module=1000, heaps_per_module=2
         "assign": rel(n_assign, False),
         "load": rel(n_load, False),
         "store": rel(n_store, False),
+    }
+
+
+def call_graph_input(seed: int, n_types=2000, methods_per_type=4, instrs_per_method=8,
+                     vars_per_method=4, heaps_per_method=3, moves_per_method=6,
+                     object_sigs=12, n_sigs=20000, p_override=0.3, p_object_call=0.5,
+                     p_object_type=0.3, p_cross_move=0.2, entry_frac=0.01, zipf=1.1,
+                     type_zipf=0.5) -> dict:
+    """Inputs of a context-insensitive call-graph analysis, shaped like the
+    relations micro-doop's CallGraphEdge rule joins (Sec. 5).
+
+    Types form a tree under type 0 (the universal base class; each type's
+    parent is 0 with probability 1/2, else a uniform earlier type).  Type 0
+    declares ``object_sigs`` signatures; every other type declares
+    ``methods_per_type`` distinct ones, each an override of a base-class
+    signature with probability ``p_override``, else drawn by Zipf(``zipf``)
+    popularity.  A signature s is the pair (sn, dsc) = (s >> 4, s & 15).
+    Method lookup resolves every signature visible in a type to its nearest
+    declaring ancestor, so the base class's signatures resolve in every type:
+    the skew buried inside the rule.  Every local variable has a declared
+    type (type 0 with probability ``p_object_type``, else drawn by
+    Zipf(``type_zipf``) popularity).
+    Each method has ``instrs_per_method`` instructions, half of them virtual
+    calls on one of its locals, to a base-class signature with probability
+    ``p_object_call``, else to a signature visible in that local's declared
+    type; it allocates ``heaps_per_method`` objects of their local's declared
+    type; and it has ``moves_per_method`` moves between its locals, a
+    fraction ``p_cross_move`` of them into a local of another method
+    (argument passing).  A fraction ``entry_frac`` of the methods (at least
+    one) are entry points, reachable from the start.
+
+    Returns {"Reachable": (j,), "Instruction_Method": (i, j),
+    "VirtualMethodInvoc": (i, b, sn, dsc), "Alloc": (v, h, j),
+    "HeapAllocation_Type": (h, t), "MethodLookup": (sn, dsc, t, m),
+    "Move": (to, from)} as uint32 arrays.
+    """
+    g = rng(seed)
+    T = n_types
+    parent = np.where(g.random(T) < 0.5, 0, np.floor(g.random(T) * np.arange(T))).astype(np.int64)
+    zw = np.arange(1, n_sigs - object_sigs + 1, dtype=np.float64) ** (-zipf)
+    zcdf = np.cumsum(zw / zw.sum())
+    # Declarations (type, signature) -> method id, base class first.
+    decl_t = [np.zeros(object_sigs, np.int64)]
+    decl_s = [np.arange(object_sigs, dtype=np.int64)]
+    for t in range(1, T):
+        sigs = set()
+        while len(sigs) < methods_per_type:
+            if g.random() < p_override:
+                sigs.add(int(g.integers(0, object_sigs)))
+            else:
+                k = int(np.searchsorted(zcdf, g.random(), side="right"))
+                sigs.add(object_sigs + min(k, n_sigs - object_sigs - 1))
+        decl_t.append(np.full(len(sigs), t, np.int64))
+        decl_s.append(np.array(sorted(sigs), np.int64))
+    dt, ds = np.concatenate(decl_t), np.concatenate(decl_s)
+    M = len(dt)
+    # Lookup tables down the type tree (parents precede children).
+    declared = [dict() for _ in range(T)]
+    for m in range(M):
+        declared[int(dt[m])][int(ds[m])] = m
+    visible = [None] * T
+    visible[0] = dict(declared[0])
+    for t in range(1, T):
+        v = dict(visible[int(parent[t])])
+        v.update(declared[t])
+        visible[t] = v
+    ml = np.array([(s >> 4, s & 15, t, m) for t in range(T) for s, m in visible[t].items()],
+                  dtype=np.uint32)
+    vis_len = np.array([len(visible[t]) for t in range(T)], np.int64)
+    vis_off = np.concatenate([[0], np.cumsum(vis_len)[:-1]])
+    vis_sig = np.array([s for t in range(T) for s in visible[t]], np.int64)
+    # Locals and their declared types.
+    tw = np.arange(1, T, dtype=np.float64) ** (-type_zipf)
+    tcdf = np.cumsum(tw / tw.sum())
+    nv = M * vars_per_method
+    vtype = np.where(g.random(nv) < p_object_type, 0,
+                     1 + np.minimum(np.searchsorted(tcdf, g.random(nv), side="right"), T - 2))
+    # Method bodies.
+    I = M * instrs_per_method
+    instr = np.arange(I, dtype=np.int64)
+    in_method = instr // instrs_per_method
+    calls = instr[g.random(I) < 0.5]
+    base = in_method[calls] * vars_per_method + g.integers(0, vars_per_method, len(calls))
+    bt = vtype[base]
+    typed = vis_sig[vis_off[bt] + np.floor(g.random(len(calls)) * vis_len[bt]).astype(np.int64)]
+    sig = np.where(g.random(len(calls)) < p_object_call, g.integers(0, object_sigs, len(calls)), typed)
+    vmi = np.stack([calls, base, sig >> 4, sig & 15], axis=1)
+    H = M * heaps_per_method
+    heap = np.arange(H, dtype=np.int64)
+    owner = heap // heaps_per_method
+    into = owner * vars_per_method + g.integers(0, vars_per_method, H)
+    alloc = np.stack([into, heap, owner], axis=1)
+    nm = M * moves_per_method
+    src_m = np.repeat(np.arange(M, dtype=np.int64), moves_per_method)
+    dst_m = np.where(g.random(nm) < p_cross_move, g.integers(0, M, nm), src_m)
+    frm = src_m * vars_per_method + g.integers(0, vars_per_method, nm)
+    to = dst_m * vars_per_method + g.integers(0, vars_per_method, nm)
+    keep = frm != to
+    move = np.unique(np.stack([to[keep], frm[keep]], axis=1), axis=0)
+    entries = np.sort(g.choice(M, size=max(1, int(M * entry_frac)), replace=False))
+
+    def u32(a):
+        return np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+
+    return {
+        "Reachable": u32(entries.reshape(-1, 1)),
+        "Instruction_Method": u32(np.stack([instr, in_method], axis=1)),
+        "VirtualMethodInvoc": u32(vmi),
+        "Alloc": u32(alloc),
+        "HeapAllocation_Type": u32(np.stack([heap, vtype[into]], axis=1)),
+        "MethodLookup": ml,
+        "Move": u32(move),
     }
 
 

@@ -298,3 +298,61 @@ def points_to(address_of, assign, load, store) -> set:
                 work.append(v)
                 inq.add(v)
     return {(v, h) for v, s in pts.items() for h in s}
+
+
+def call_graph(rel: dict) -> tuple:
+    """Context-insensitive call-graph construction by a worklist: a reachable
+    method's allocations put their objects in its locals; moves copy a
+    local's objects into another local; a virtual call in a reachable method
+    on a local holding an object of type t, with signature (sn, dsc), calls
+    the method that lookup gives for (sn, dsc, t), which becomes reachable.
+    Returns (reachable methods, {(h, v)} points-to, {(i, m)} call edges)."""
+    method_of = dict(map(tuple, np.asarray(rel["Instruction_Method"]).tolist()))
+    calls_in = defaultdict(list)          # method -> [(i, b, sn, dsc)]
+    for i, b, sn, dsc in np.asarray(rel["VirtualMethodInvoc"]).tolist():
+        calls_in[method_of[i]].append((i, b, sn, dsc))
+    allocs_in = defaultdict(list)         # method -> [(v, h)]
+    for v, h, j in np.asarray(rel["Alloc"]).tolist():
+        allocs_in[j].append((v, h))
+    type_of = dict(map(tuple, np.asarray(rel["HeapAllocation_Type"]).tolist()))
+    lookup = defaultdict(set)
+    for sn, dsc, t, m in np.asarray(rel["MethodLookup"]).tolist():
+        lookup[(sn, dsc, t)].add(m)
+    moves_from = defaultdict(set)         # from -> {to}
+    for to, frm in np.asarray(rel["Move"]).tolist():
+        moves_from[frm].add(to)
+    calls_on = defaultdict(list)          # local -> calls on it in reachable methods
+    heaps = defaultdict(set)
+    reach, edges = set(), set()
+    work_m = deque(int(j) for j in np.asarray(rel["Reachable"]).ravel().tolist())
+    work_v = deque()
+
+    def add_heap(v, h):
+        if h not in heaps[v]:
+            heaps[v].add(h)
+            work_v.append((v, h))
+
+    while work_m or work_v:
+        while work_m:
+            j = work_m.popleft()
+            if j in reach:
+                continue
+            reach.add(j)
+            for v, h in allocs_in[j]:
+                add_heap(v, h)
+            for c in calls_in[j]:
+                calls_on[c[1]].append(c)
+                for h in list(heaps[c[1]]):
+                    for m in lookup.get((c[2], c[3], type_of[h]), ()):
+                        edges.add((c[0], m))
+                        work_m.append(m)
+        while work_v:
+            v, h = work_v.popleft()
+            for to in moves_from[v]:
+                add_heap(to, h)
+            for i, _, sn, dsc in calls_on[v]:
+                for m in lookup.get((sn, dsc, type_of[h]), ()):
+                    edges.add((i, m))
+                    work_m.append(m)
+    pts = {(h, v) for v, hs in heaps.items() for h in hs}
+    return reach, pts, edges

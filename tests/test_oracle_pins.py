@@ -24,8 +24,8 @@ import scipy.sparse as sp
 
 import oracle
 from paper_2604_20073_amd import workloads as W
-from tests.checkers import (Rule, as_sorted_array, bfs_layers, brute_force, naive_rounds,
-                            points_to, render)
+from tests.checkers import (Rule, as_sorted_array, bfs_layers, brute_force, call_graph,
+                            naive_rounds, points_to, render)
 
 TC = "path(x,y) :- edge(x,y).\npath(x,z) :- path(x,y), edge(y,z)."
 TRI = "tri(x,y,z) :- edge(x,y), edge(y,z), edge(x,z)."
@@ -430,6 +430,108 @@ def test_helper_split_pointsto_same_model():
         expect = as_sorted_array(points_to(rel["addressOf"], rel["assign"], rel["load"],
                                            rel["store"]), 2)
         assert np.array_equal(split["pt"], expect)
+
+
+SAME_GEN = ("sg(x,y) :- par(p,x), par(p,y), x != y.\n"
+            "sg(x,y) :- par(a,x), sg(a,b), par(b,y).")
+
+
+@pytest.mark.parametrize("side", [3, 5, 12])
+def test_same_generation_on_a_mesh_closed_form(side):
+    """Same generation over a grid mesh with edges both ways: two nodes are
+    of the same generation iff they have the same colour in the grid's
+    2-colouring (walks of equal length from a common node exist exactly
+    then, the node itself included), so sg holds every same-colour pair
+    (n^2/2 rows for even n); the pair of opposite corners first appears at depth
+    side - 1, so for side >= 3 the run records side deltas (the base
+    round's first, the last one empty)."""
+    par = W.mesh_graph(side, 40 + side)
+    n = side * side
+    adj = sp.csr_matrix((np.ones(len(par)), (par[:, 0], par[:, 1])), shape=(n, n))
+    colour = np.full(n, -1)
+    colour[0], frontier = 0, [0]
+    while frontier:
+        nxt = []
+        for u in frontier:
+            for v in adj.indices[adj.indptr[u]:adj.indptr[u + 1]]:
+                if colour[v] < 0:
+                    colour[v] = 1 - colour[u]
+                    nxt.append(v)
+        frontier = nxt
+    assert (colour >= 0).all()
+    expect = np.array([(x, y) for x in range(n) for y in range(n) if colour[x] == colour[y]],
+                      dtype=np.uint32).reshape(-1, 2)
+    o, got = oracle.evaluate({"par": 2, "sg": 2}, SAME_GEN, {"par": par})
+    ones = int(colour.sum())
+    assert len(expect) == (n - ones) ** 2 + ones ** 2 and abs(n - 2 * ones) <= 1
+    assert np.array_equal(got["sg"], expect)
+    assert len(o.delta_sizes("sg")) == side
+
+
+def test_binary_join_chain_same_model():
+    """A body of three or more atoms rewritten into a left-deep chain of
+    two-atom joins through helper relations (the plan of a binary-join
+    engine, Sec. 7.2) has the same least model on the declared relations:
+    same generation, the 4-clique rule with its comparisons, points-to."""
+    par = W.mesh_graph(7, 3)
+    _, a = oracle.evaluate({"par": 2, "sg": 2}, SAME_GEN, {"par": par})
+    chain = ("sg(x,y) :- par(p,x), par(p,y), x != y.\n"
+             "h(x,b) :- par(a,x), sg(a,b).\nsg(x,y) :- par(b,y), h(x,b).")
+    _, b = oracle.evaluate({"par": 2, "sg": 2, "h": 2}, chain, {"par": par})
+    assert np.array_equal(a["sg"], b["sg"])
+    edges = W.rmat_graph(8, 1500, 5)
+    _, a = oracle.evaluate({"edge": 2, "q": 4}, Q4, {"edge": edges})
+    chain = ("h1(w,x) :- edge(w,x), w < x.\n"
+             "h2(w,x,y) :- edge(x,y), h1(w,x), x < y.\n"
+             "h3(w,x,y) :- edge(w,y), h2(w,x,y), w < y.\n"
+             "h4(w,x,y,z) :- edge(y,z), h3(w,x,y), y < z.\n"
+             "h5(w,x,y,z) :- edge(x,z), h4(w,x,y,z), x < z.\n"
+             "q(w,x,y,z) :- edge(w,z), h5(w,x,y,z), w < z.")
+    _, b = oracle.evaluate({"edge": 2, "q": 4, "h1": 2, "h2": 3, "h3": 3, "h4": 4, "h5": 4},
+                           chain, {"edge": edges})
+    assert len(a["q"]) > 100 and np.array_equal(a["q"], b["q"])
+    rel = W.andersen(31, n_modules=3, vars_per_module=40, heaps_per_module=9,
+                     n_address_of=30, n_assign=90, n_load=30, n_store=30)
+    names = {"addressOf": 2, "assign": 2, "load": 2, "store": 2, "pt": 2}
+    _, a = oracle.evaluate(names, ANDERSEN, rel)
+    chain = ("pt(v,h) :- addressOf(v,h).\npt(v,h) :- assign(v,w), pt(w,h).\n"
+             "l(v,q) :- load(v,p), pt(p,q).\npt(v,h) :- pt(q,h), l(v,q).\n"
+             "s(w,q) :- store(p,w), pt(p,q).\npt(q,h) :- pt(w,h), s(w,q).")
+    _, b = oracle.evaluate(dict(names, l=2, s=2), chain, rel)
+    assert np.array_equal(a["pt"], b["pt"])
+
+
+CALL_GRAPH = (
+    "VarPointsTo(h,v) :- Reachable(j), Alloc(v,h,j).\n"
+    "VarPointsTo(h,to) :- Move(to,from), VarPointsTo(h,from).\n"
+    "CallGraphEdge(i,m) :- Reachable(j), Instruction_Method(i,j), VirtualMethodInvoc(i,b,sn,dsc), "
+    "VarPointsTo(h,b), HeapAllocation_Type(h,t), MethodLookup(sn,dsc,t,m).\n"
+    "Reachable(m) :- CallGraphEdge(i,m).")
+CALL_GRAPH_RELS = {"Reachable": 1, "Instruction_Method": 2, "VirtualMethodInvoc": 4, "Alloc": 3,
+                   "HeapAllocation_Type": 2, "MethodLookup": 4, "Move": 2, "VarPointsTo": 2,
+                   "CallGraphEdge": 2}
+# The paper's targeted split of the CallGraphEdge rule (Sec. 5): method lookup
+# and the allocation type factored into HelpNT, exposing sn, dsc, m and h.
+CALL_GRAPH_SPLIT = CALL_GRAPH.replace(
+    "VarPointsTo(h,b), HeapAllocation_Type(h,t), MethodLookup(sn,dsc,t,m).",
+    "VarPointsTo(h,b), HelpNT(sn,dsc,m,h).\n"
+    "HelpNT(sn,dsc,m,h) :- MethodLookup(sn,dsc,t,m), HeapAllocation_Type(h,t).")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_call_graph_worklist_and_split(seed):
+    """The six-atom recursive CallGraphEdge program equals a worklist
+    call-graph construction, and so does its split form."""
+    rel = W.call_graph_input(300 + seed, n_types=150 + 50 * seed)
+    reach, pts, edges = call_graph(rel)
+    assert len(edges) > 20 and len(reach) > len(rel["Reachable"])
+    o, got = oracle.evaluate(CALL_GRAPH_RELS, CALL_GRAPH, rel)
+    assert np.array_equal(got["Reachable"], as_sorted_array({(j,) for j in reach}, 1))
+    assert np.array_equal(got["VarPointsTo"], as_sorted_array(pts, 2))
+    assert np.array_equal(got["CallGraphEdge"], as_sorted_array(edges, 2))
+    _, split = oracle.evaluate(dict(CALL_GRAPH_RELS, HelpNT=4), CALL_GRAPH_SPLIT, rel)
+    for n in ("Reachable", "VarPointsTo", "CallGraphEdge"):
+        assert np.array_equal(split[n], got[n]), n
 
 
 @pytest.mark.parametrize("seed", [0, 1])

@@ -105,3 +105,16 @@ def test_serving_trace_and_facts():
             e = f["edge_tc"]
             assert len(e) == 1024 * -(-r["m"] // 1024)
             assert np.array_equal(e[:, 0] // 256, e[:, 1] // 256)   # disjoint components
+
+
+def test_mesh_graph_is_a_symmetric_grid():
+    side = 9
+    g = W.mesh_graph(side, 5)
+    assert g.shape == (4 * side * (side - 1), 2) and g.dtype == np.uint32
+    pairs = set(map(tuple, g.tolist()))
+    assert len(pairs) == len(g)
+    assert all((v, u) in pairs for u, v in pairs)          # both directions
+    deg = np.bincount(g[:, 0], minlength=side * side)
+    assert sorted(np.bincount(deg).nonzero()[0].tolist()) == [2, 3, 4]
+    assert np.bincount(deg)[2] == 4                         # the corners
+    assert np.array_equal(W.mesh_graph(side, 5), g)
