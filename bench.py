@@ -237,6 +237,87 @@ def bench_sg(args):
         sys.exit(1)
 
 
+CALL_GRAPH = (
+    "VarPointsTo(h,v) :- Reachable(j), Alloc(v,h,j).\n"
+    "VarPointsTo(h,to) :- Move(to,from), VarPointsTo(h,from).\n"
+    "CallGraphEdge(i,m) :- Reachable(j), Instruction_Method(i,j), VirtualMethodInvoc(i,b,sn,dsc), "
+    "VarPointsTo(h,b), HeapAllocation_Type(h,t), MethodLookup(sn,dsc,t,m).\n"
+    "Reachable(m) :- CallGraphEdge(i,m).")
+CALL_GRAPH_RELS = {"Reachable": 1, "Instruction_Method": 2, "VirtualMethodInvoc": 4, "Alloc": 3,
+                   "HeapAllocation_Type": 2, "MethodLookup": 4, "Move": 2, "VarPointsTo": 2,
+                   "CallGraphEdge": 2}
+
+
+def bench_cg(args):
+    """The six-atom recursive CallGraphEdge rule (Sec. 5) over a synthetic
+    call-graph analysis input: as written, with the paper's targeted split
+    (HelpNT from method lookup and allocation type), and as a binary-join
+    chain; time, join-kernel time and rounds for each, relations compared
+    across plans."""
+    import torch
+
+    from paper_2604_20073_amd import Engine
+    from paper_2604_20073_amd import workloads as W
+
+    rel = W.call_graph_input(W.SEED_BASE + 7, n_types=args.cg_types)
+    log("call-graph input: " + ", ".join(f"{k} {len(v)}" for k, v in rel.items()))
+    dev = {k: torch.from_numpy(v.view(np.int32)).cuda() for k, v in rel.items()}
+    outs = ("Reachable", "VarPointsTo", "CallGraphEdge")
+    result, rows = {}, {}
+    for plan in ("as_written", "split", "binary"):
+        e = Engine(device=0, wg_per_cu=args.wg_per_cu, flags=args.flags)
+        for n, k in CALL_GRAPH_RELS.items():
+            e.declare(n, k)
+        e.add_rules(CALL_GRAPH)
+        if plan == "split":
+            e.split_rule(2, [4, 5])
+        elif plan == "binary":
+            e.binary_plan()
+        for n, t in dev.items():
+            e.load(n, t)
+        for i in range(args.warmup):
+            st = e.run()
+            log(f"{plan} warmup {i}: {st['wall_ms']:.1f} ms, rounds={st['rounds']}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = []
+        for i in range(args.steps):
+            stats.append(e.run())
+            log(f"{plan} step {i}: {stats[-1]['wall_ms']:.1f} ms")
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+
+        def avg(key):
+            return {k: round(sum(x[key][k] for x in stats) / args.steps, 2) for k in stats[0][key]}
+        result[plan] = {"ms_per_step": round(ms, 3), "rounds": stats[0]["rounds"],
+                        "sizes": {n: e.size(n) for n in outs},
+                        "candidate_rows": stats[0]["candidate_rows"],
+                        "intermediate_rows": sum(e.helper_sizes()),
+                        "phase_ms": avg("phase_ms"), "kernel_ms": avg("kernel_ms")}
+        rows[plan] = {n: e.read_numpy(n) for n in outs}
+        e.close()
+    same = all(np.array_equal(rows[p][n], rows["as_written"][n])
+               for p in ("split", "binary") for n in outs)
+    a = result["as_written"]
+    derived = sum(a["sizes"].values())
+    out = {"metric": "derived tuples/sec to fixpoint", "value": round(derived / (a["ms_per_step"] / 1e3), 1),
+           "unit": "tuples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": a["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": (f"call-graph analysis, {args.cg_types} types: the six-atom "
+                                   "recursive CallGraphEdge rule"),
+                      "inputs": {k: len(v) for k, v in rel.items()}},
+           "plans": result,
+           "split_speedup": round(a["ms_per_step"] / result["split"]["ms_per_step"], 3),
+           "split_join_kernel_speedup": round(
+               a["kernel_ms"]["join_count"] / max(result["split"]["kernel_ms"]["join_count"], 1e-3), 3),
+           "same_relations": same}
+    print(json.dumps(out), flush=True)
+    if not same:
+        log("the plans differ")
+        sys.exit(1)
+
+
 def bench_batch(args):
     """Many small instances: TC + triangles on seeded ER graphs, n log-uniform
     in [50, 5000], 4 out-edges per node.  All instances run in batched
@@ -255,7 +336,7 @@ def bench_batch(args):
     log(f"generating {args.instances} instances")
     graphs = [W.batch_instance(cseed, i, int(n)) for i, n in enumerate(sizes)]
     est = 0.96 * sizes.astype(np.float64) ** 2  # closure rows of a strongly connected ER graph
-    budget = 1.5e9                               # closure rows per sub-batch
+    budget = args.batch_rows                     # closure rows per sub-batch
     order = np.argsort(sizes, kind="stable")
     batches, cur, acc = [], [], 0.0
     for i in order:
@@ -523,7 +604,10 @@ def main():
                     help="serve: start no plain request after this many seconds (0: none)")
     ap.add_argument("--sizes-out", default="", help="serve: write per-request result sizes here")
     ap.add_argument("--mesh-side", type=int, default=111, help="sg: grid side of the mesh")
-    ap.add_argument("--workload", choices=["rmat", "andersen", "batch", "serve", "sg"], default="rmat",
+    ap.add_argument("--batch-rows", type=float, default=1.5e9,
+                    help="batch: estimated closure rows per sub-batch (1e11: one batch)")
+    ap.add_argument("--cg-types", type=int, default=50000, help="cg: number of types")
+    ap.add_argument("--workload", choices=["rmat", "andersen", "batch", "serve", "sg", "cg"], default="rmat",
                     help="rmat: the skewed cyclic-join configuration (default, the headline); "
                          "andersen: the recursive points-to configuration (1M variables, "
                          "200k heap sites, 3.5M input tuples)")
@@ -565,6 +649,8 @@ def main():
         return bench_serve(args)
     if args.workload == "sg":
         return bench_sg(args)
+    if args.workload == "cg":
+        return bench_cg(args)
 
     log(f"generating R-MAT scale {args.scale}, {args.edges} edges")
     edges = W.rmat_graph(args.scale, args.edges, W.SEED_BASE + 1)

@@ -95,6 +95,14 @@ typedef int32_t wcdl_status;
                                     already had (Sec. 2: deltas are the new facts
                                     of a round); a failure is WCDL_E_CHECK.
                                     Costs one pass over the relation per merge. */
+#define WCDL_F_COST_PLANNER 0x400u /* choose each rule version's variable order
+                                    by a cost model over per-column distinct
+                                    counts of the body relations (the paper's
+                                    future work on variable orders, Sec. 9)
+                                    instead of the structural heuristic (most
+                                    shared variable first, delta-first); rules
+                                    with a user order, batched engines and
+                                    serving keep theirs */
 #define WCDL_F_BATCHED 0x10u     /* batched mode: the engine holds many independent
                                     instances of one program.  Every relation gets
                                     an implicit leading column, the instance id:
@@ -371,6 +379,33 @@ wcdl_status wcdl_read_rows(const wcdl_engine* e, uint32_t rel, uint64_t first, u
  * hold the last candidate's (identical) results afterwards. */
 wcdl_status wcdl_autotune(wcdl_engine* e, const uint32_t* wg_per_cu, uint32_t n, uint32_t* chosen,
                           double* best_ms);
+
+/* Strategy flags the configuration tuner may set or clear. */
+#define WCDL_TUNE_FLAGS (WCDL_F_STREAMS_OFF | WCDL_F_XPROD_OFF | WCDL_F_STAGE_OFF | \
+                         WCDL_F_HEAD_BODY_OFF | WCDL_F_RUN_BITMAPS_OFF |            \
+                         WCDL_F_GROUPED_SORT_OFF | WCDL_F_COST_PLANNER)
+
+/* One configuration for wcdl_autotune_points: the partition granularity, the
+ * count-pass staging arena size (0 = default) and the strategy flags (only
+ * bits of WCDL_TUNE_FLAGS; the engine's other flags are kept). */
+typedef struct {
+  uint32_t wg_per_cu;
+  uint32_t stage_pct;
+  uint32_t flags;
+} wcdl_tune_point;
+
+/* Configuration tuner: run the program once per point, keep the fastest
+ * point's settings for later runs, report its index in *chosen and its run
+ * time in *best_ms.  Choices are remembered for the process, keyed by the
+ * program (rules up to variable names) and the size bucket of its loaded
+ * facts (floor of log2 of their row count): a later call with the same key
+ * and the same points applies the remembered choice without running (then
+ * *best_ms is the time measured when it was chosen).  The relations hold
+ * the results of the last run (identical for every point).  Fails with
+ * WCDL_E_INVALID on an empty list, a zero wg_per_cu or flags outside
+ * WCDL_TUNE_FLAGS. */
+wcdl_status wcdl_autotune_points(wcdl_engine* e, const wcdl_tune_point* points, uint32_t n,
+                                 uint32_t* chosen, double* best_ms);
 
 /* ---- Continuous evaluation (serving), batched engines only -------------
  *

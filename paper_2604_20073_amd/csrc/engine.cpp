@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cstdio>
 #include <functional>
+#include <limits>
 #include <memory>
 #include <numeric>
 #include <set>
@@ -315,7 +316,10 @@ struct wcdl_engine {
   std::map<std::string, uint32_t> rel_ids;
   std::vector<wcdl::Rule> rules;
   std::string err;
-  uint64_t* pinned = nullptr;  // host-pinned scratch for device->host scalars
+  // Pinned host copies of rule-version plans, one per version of the
+  // largest batch so far, kept for the engine's lifetime (a plan is staged
+  // here before its asynchronous upload).
+  std::vector<void*> plan_staging;
   uint32_t helper_count = 0;
   std::map<std::string, uint32_t> helper_keys;  // canonical helper definition -> relation
   wcdl_run_stats last{};
@@ -332,6 +336,9 @@ struct wcdl_engine {
   // per-instance memory cap.
   uint32_t max_instance = 0;
   std::set<uint32_t> rejected;
+  // Cost planner: distinct values per column of each relation, with the row
+  // count they were taken at (recomputed when it changes).
+  std::map<uint32_t, std::pair<uint64_t, std::vector<uint64_t>>> col_stats;
 };
 
 // An instance of a batched engine's program: its rows carry `id` in the
@@ -654,6 +661,150 @@ std::vector<u32> choose_order(const Rule& r, int delta_atom) {
   return order;
 }
 
+// ---------------------------------------------------------------------------
+// Cost-model variable order (the paper's future work on variable orders,
+// Sec. 9).  Statistics: rows and distinct values per column of every body
+// relation (one sort per column, cached while the row count is unchanged).
+// Estimate for an order, under independence: a level's candidates are the
+// bindings of the level above times the smallest per-binding fan-out among
+// the atoms holding its variable (the intersection's driver); the other
+// atoms keep a fraction fan-out / domain of them, and a comparison between
+// bound variables keeps half.  Cost = candidates over all levels weighted by
+// the sources each candidate is probed in, plus the output rows times the
+// cost of sorting them (none when emitted in order, less when grouped by
+// all but the last head column).  Delta-first as in the heuristic (Sec.
+// 7.3): the root is one of the delta atom's variables.
+// ---------------------------------------------------------------------------
+
+const std::vector<u64>& relation_ndv(Engine* e, u32 rel) {
+  Relation& R = e->rels[rel];
+  auto it = e->col_stats.find(rel);
+  if (it != e->col_stats.end() && it->second.first == R.full.n) return it->second.second;
+  std::vector<u64> ndv(R.arity, 0);
+  for (u32 c = 0; c < R.arity && R.full.n; ++c) {
+    const u32 pos = (u32)(std::find(R.full.order.begin(), R.full.order.end(), c) - R.full.order.begin());
+    std::vector<const u32*> in{R.full.col[pos].get()};
+    ndv[c] = sort_rows(e, 0, {0u}, in, R.full.n, true).n;
+  }
+  auto& slot = e->col_stats[rel];
+  slot = {R.full.n, std::move(ndv)};
+  return slot.second;
+}
+
+double order_cost(Engine* e, const Rule& r, int delta_atom, const std::vector<u32>& order,
+                  const std::vector<std::vector<u64>>& ndv, const std::vector<double>& rows) {
+  const u32 nv = r.nvars;
+  std::vector<bool> bound(nv, false);
+  // Domain estimate per variable: the most distinct values any atom has for it.
+  std::vector<double> dom(nv, 1.0);
+  for (size_t a = 0; a < r.body.size(); ++a)
+    for (size_t c = 0; c < r.body[a].t.size(); ++c)
+      if (r.body[a].t[c].var) dom[r.body[a].t[c].v] = std::max(dom[r.body[a].t[c].v], (double)ndv[a][c]);
+  double n = 1.0, cost = 0.0;
+  for (u32 v : order) {
+    // Per-binding fan-out of v in every atom holding it.
+    std::vector<double> fan;
+    for (size_t a = 0; a < r.body.size(); ++a) {
+      bool has = false;
+      double sel = rows[a];
+      for (size_t c = 0; c < r.body[a].t.size(); ++c) {
+        const Term& t = r.body[a].t[c];
+        if (t.var && t.v == v) has = true;
+        else if (!t.var || bound[t.v]) sel /= std::max<double>(1.0, (double)ndv[a][c]);
+      }
+      if (!has) continue;
+      double nd = 1.0;
+      for (size_t c = 0; c < r.body[a].t.size(); ++c)
+        if (r.body[a].t[c].var && r.body[a].t[c].v == v) nd = std::max(nd, (double)ndv[a][c]);
+      fan.push_back(std::max(std::min(sel, nd), 1e-9));
+    }
+    std::sort(fan.begin(), fan.end());
+    const double examined = n * fan[0];
+    cost += examined * (double)fan.size();
+    double keep = fan[0];
+    for (size_t i = 1; i < fan.size(); ++i) keep *= std::min(1.0, fan[i] / dom[v]);
+    bound[v] = true;
+    for (auto& c : r.cmps)
+      if (c.a.var && c.b.var && (c.a.v == v || c.b.v == v) && bound[c.a.v] && bound[c.b.v]) keep *= 0.5;
+    n *= keep;
+  }
+  // Output order: rows in head order need no sort; grouped by all but the
+  // last head column, a cheap one; else the radix passes.
+  u32 prefix = 0;
+  for (size_t h = 0; h < r.head.t.size() && h < order.size(); ++h) {
+    if (!r.head.t[h].var || r.head.t[h].v != order[h]) break;
+    ++prefix;
+  }
+  const size_t hk = r.head.t.size();
+  const double sort_cost = delta_atom < 0 && prefix == hk && hk == order.size() ? 0.0
+                           : prefix + 1 >= hk ? 1.0 : 6.0;
+  (void)e;
+  return cost + n * sort_cost;
+}
+
+// Lowest-cost connected order, or empty when no statistics apply.
+std::vector<u32> cost_order(Engine* e, const Rule& r, int delta_atom) {
+  std::vector<std::vector<u64>> ndv;
+  std::vector<double> rows;
+  for (size_t a = 0; a < r.body.size(); ++a) {
+    const Relation& R = e->rels[r.body[a].rel];
+    ndv.push_back(relation_ndv(e, r.body[a].rel));
+    // A delta is estimated at the relation's size: the first round's delta
+    // is the whole relation.
+    rows.push_back(std::max<double>(1.0, (double)R.full.n));
+  }
+  std::vector<u32> vars;
+  for (auto& a : r.body)
+    for (auto& t : a.t)
+      if (t.var && std::find(vars.begin(), vars.end(), t.v) == vars.end()) vars.push_back(t.v);
+  std::vector<u32> roots;
+  if (delta_atom >= 0) {
+    for (auto& t : r.body[delta_atom].t)
+      if (t.var && std::find(roots.begin(), roots.end(), t.v) == roots.end()) roots.push_back(t.v);
+  } else {
+    roots = vars;
+  }
+  std::vector<u32> best, cur;
+  double best_cost = std::numeric_limits<double>::infinity();
+  std::vector<bool> used(r.nvars, false);
+  auto connected = [&](u32 w) {  // w shares an atom with a bound variable
+    for (auto& a : r.body) {
+      bool hw = false, hb = false;
+      for (auto& t : a.t)
+        if (t.var) {
+          if (t.v == w) hw = true;
+          else if (used[t.v]) hb = true;
+        }
+      if (hw && hb) return true;
+    }
+    return false;
+  };
+  std::function<void()> dfs = [&] {
+    if (cur.size() == vars.size()) {
+      const double c = order_cost(e, r, delta_atom, cur, ndv, rows);
+      if (c < best_cost) best_cost = c, best = cur;
+      return;
+    }
+    for (u32 v : (cur.empty() ? roots : vars)) {
+      if (used[v]) continue;
+      if (!cur.empty()) {
+        // Only variables that share an atom with a bound one, while any do.
+        bool any = false;
+        for (u32 w : vars)
+          if (!used[w] && connected(w)) any = true;
+        if (any && !connected(v)) continue;
+      }
+      used[v] = true;
+      cur.push_back(v);
+      dfs();
+      cur.pop_back();
+      used[v] = false;
+    }
+  };
+  dfs();
+  return best;
+}
+
 // Build a version of rule `ri` with atom `delta_atom` read from the delta (or
 // -1 for none).  Pointers are filled later.
 Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
@@ -663,6 +814,11 @@ Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
   v.delta_atom = delta_atom;
   v.head_rel = r.head.rel;
   v.level_var = choose_order(r, delta_atom);
+  if ((flags & WCDL_F_COST_PLANNER) && r.var_order.empty() && !(e->cfg.flags & WCDL_F_BATCHED) &&
+      !e->serving) {
+    std::vector<u32> o = cost_order(e, r, delta_atom);
+    if (o.size() == v.level_var.size()) v.level_var = std::move(o);
+  }
   const u32 m = (u32)v.level_var.size();
   if (m == 0) throw Error(WCDL_E_UNSUPPORTED, "rule without body variables");
   if (m > (u32)MAXV) throw Error(WCDL_E_UNSUPPORTED, "rule has more than 8 variables");
@@ -1224,17 +1380,15 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
   const u32 flags = e->cfg.flags;
   std::vector<VRun> runs(vs.size());
   static_assert(sizeof(DPlan) < 16384, "plan size");
-  // Pinned staging for plans (one slot per version) and scalars.
-  std::vector<DPlan*> staging;
-  for (size_t i = 0; i < vs.size(); ++i) {
+  // Pinned staging for plans (one slot per version), grown as needed; the
+  // streams are idle first, so no upload of an earlier batch (one that ended
+  // early by an error included) still reads a slot.
+  sync_all(e);
+  while (e->plan_staging.size() < vs.size()) {
     void* h = nullptr;
     WCDL_HIP(hipHostMalloc(&h, sizeof(DPlan), hipHostMallocDefault));
-    staging.push_back(static_cast<DPlan*>(h));
+    e->plan_staging.push_back(h);
   }
-  struct Staging {
-    std::vector<DPlan*>& v;
-    ~Staging() { for (auto* p : v) (void)hipHostFree(p); }
-  } guard{staging};
 
   auto t_index = Clock::now();
   // ---- Inputs: every version's sorted copies.  Missing column orders are
@@ -1244,7 +1398,7 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     Version& v = vs[i];
     R.v = &v;
     R.si = seq ? 0 : i % e->streams.size();
-    R.host_plan = staging[i];
+    R.host_plan = static_cast<DPlan*>(e->plan_staging[i]);
     if (v.dead) { R.skip = true; continue; }
     DPlan& P = v.plan;
     for (size_t ai = 0; ai < v.atoms.size(); ++ai) {
@@ -2337,6 +2491,13 @@ namespace wcdl {
 // Canonical text of a helper rule: variables renamed by first occurrence
 // (head, then body, then comparisons); comparisons sorted.  Two helpers with
 // equal keys define the same relation.
+// Tuner choices of this process: (program key, size bucket, points key) ->
+// (chosen index, its run time).
+std::map<std::string, std::pair<u32, double>>& tune_memo() {
+  static std::map<std::string, std::pair<u32, double>> m;
+  return m;
+}
+
 std::string helper_key(const Rule& h) {
   std::map<u32, u32> ren;
   auto term = [&](const Term& t) {
@@ -2535,6 +2696,7 @@ void wcdl_destroy(wcdl_engine* e) {
   for (auto s : e->streams) (void)hipStreamSynchronize(s);
   e->rels.clear();
   e->mem.reset();
+  for (void* p : e->plan_staging) (void)hipHostFree(p);
   if (e->own_streams)
     for (auto s : e->streams) (void)hipStreamDestroy(s);
   delete e;
@@ -2929,6 +3091,62 @@ wcdl_status wcdl_autotune(wcdl_engine* e, const uint32_t* wg_per_cu, uint32_t n,
       }
     }
     e->cfg.wg_per_cu = best;
+    if (chosen) *chosen = best;
+    if (best_ms) *best_ms = bt;
+  });
+}
+
+wcdl_status wcdl_autotune_points(wcdl_engine* e, const wcdl_tune_point* points, uint32_t n,
+                                 uint32_t* chosen, double* best_ms) {
+  return guarded(e, [&] {
+    if (!points || n == 0) throw Error(WCDL_E_INVALID, "no candidates");
+    for (u32 i = 0; i < n; ++i) {
+      if (points[i].wg_per_cu == 0) throw Error(WCDL_E_INVALID, "wg_per_cu must be positive");
+      if (points[i].flags & ~(u32)WCDL_TUNE_FLAGS) throw Error(WCDL_E_INVALID, "flag outside WCDL_TUNE_FLAGS");
+    }
+    if (e->serving) throw Error(WCDL_E_STATE, "serving");
+    std::string key;
+    for (auto& r : e->rules) {
+      for (auto& a : r.body) key += e->rels[a.rel].name + "/";
+      key += e->rels[r.head.rel].name + "|" + helper_key(r) + "\n";
+    }
+    u64 facts = 0;
+    for (auto& R : e->rels) facts += R.base.n;
+    u32 bucket = 0;
+    while ((facts >> bucket) > 1) ++bucket;
+    key += "#" + std::to_string(bucket) + "#";
+    for (u32 i = 0; i < n; ++i)
+      key += std::to_string(points[i].wg_per_cu) + "," + std::to_string(points[i].stage_pct) + "," +
+             std::to_string(points[i].flags) + ";";
+    const u32 keep = e->cfg.flags & ~(u32)WCDL_TUNE_FLAGS;
+    auto apply = [&](const wcdl_tune_point& p) {
+      e->cfg.wg_per_cu = p.wg_per_cu;
+      e->cfg.stage_pct = p.stage_pct;
+      e->cfg.flags = keep | p.flags;
+    };
+    auto hit = tune_memo().find(key);
+    if (hit != tune_memo().end()) {
+      apply(points[hit->second.first]);
+      if (chosen) *chosen = hit->second.first;
+      if (best_ms) *best_ms = hit->second.second;
+      return;
+    }
+    const wcdl_config saved = e->cfg;
+    u32 best = 0;
+    double bt = 0;
+    try {
+      for (u32 i = 0; i < n; ++i) {
+        apply(points[i]);
+        wcdl_run_stats s{};
+        run_program(e, &s);
+        if (i == 0 || s.wall_ms < bt) bt = s.wall_ms, best = i;
+      }
+    } catch (...) {
+      e->cfg = saved;
+      throw;
+    }
+    apply(points[best]);
+    tune_memo()[key] = {best, bt};
     if (chosen) *chosen = best;
     if (best_ms) *best_ms = bt;
   });

@@ -33,6 +33,7 @@ WCDL_F_HEAD_BODY_OFF = 0x20
 WCDL_F_RUN_BITMAPS_OFF = 0x40
 WCDL_F_GROUPED_SORT_OFF = 0x80
 WCDL_F_CHECKED = 0x200
+WCDL_F_COST_PLANNER = 0x400
 PHASES = ["histogram", "count", "materialize", "delta", "index", "merge", "load", "other"]
 KERNELS = ["join_count", "join_materialize", "join_histogram", "unused"]
 ERRORS = {-1: "E_INVALID", -2: "E_ARITY", -3: "E_UNKNOWN_REL", -4: "E_UNSAFE_RULE",
@@ -69,6 +70,11 @@ class _StepStats(ctypes.Structure):
                 ("resident_rows", ctypes.c_uint64), ("wall_ms", ctypes.c_double),
                 ("bound_bytes", ctypes.c_uint64), ("resident_bytes", ctypes.c_uint64),
                 ("rejected", ctypes.c_uint64), ("phase_ms", ctypes.c_double * 8)]
+
+
+class _TunePoint(ctypes.Structure):
+    _fields_ = [("wg_per_cu", ctypes.c_uint32), ("stage_pct", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
 
 
 class _Term(ctypes.Structure):
@@ -109,7 +115,7 @@ EXPORTS = [
     "wcdl_binary_plan", "wcdl_run",
     "wcdl_relation_size", "wcdl_read_columns", "wcdl_delta_sizes", "wcdl_work_slice",
     "wcdl_owner_key", "wcdl_decode_unit", "wcdl_relation_range", "wcdl_read_rows",
-    "wcdl_autotune", "wcdl_serve_begin", "wcdl_serve_admit", "wcdl_serve_step",
+    "wcdl_autotune", "wcdl_autotune_points", "wcdl_serve_begin", "wcdl_serve_admit", "wcdl_serve_step",
     "wcdl_serve_live", "wcdl_serve_release", "wcdl_serve_end",
     "wcdl_instance_create", "wcdl_instance_id", "wcdl_instance_load", "wcdl_instance_size",
     "wcdl_instance_read", "wcdl_instance_destroy", "wcdl_run_batch", "wcdl_step",
@@ -150,6 +156,8 @@ def lib():
     L.wcdl_step.argtypes = [P, ctypes.POINTER(P), u32, ctypes.POINTER(ctypes.c_uint8), pu64]
     L.wcdl_rule_count.argtypes = [P, pu32]
     L.wcdl_split_rule.argtypes = [P, u32, pu32, u32, pu32]
+    L.wcdl_autotune_points.argtypes = [P, ctypes.POINTER(_TunePoint), u32, pu32,
+                                       ctypes.POINTER(ctypes.c_double)]
     L.wcdl_binary_plan.argtypes = [P, pu32]
     L.wcdl_run.argtypes = [P, ctypes.POINTER(_Stats)]
     L.wcdl_relation_size.argtypes = [P, u32, pu64]
@@ -526,6 +534,15 @@ class Engine:
         chosen, ms = ctypes.c_uint32(), ctypes.c_double()
         self._check(self._lib.wcdl_autotune(self._e, c, len(wg_per_cu), ctypes.byref(chosen),
                                             ctypes.byref(ms)))
+        return chosen.value, ms.value
+
+    def autotune_points(self, points):
+        """Run the program once per configuration point, a (wg_per_cu,
+        stage_pct, flags) triple, keep the fastest; returns (index, ms)."""
+        arr = (_TunePoint * len(points))(*[_TunePoint(w, sp, f) for w, sp, f in points])
+        chosen, ms = ctypes.c_uint32(), ctypes.c_double()
+        self._check(self._lib.wcdl_autotune_points(self._e, arr, len(points), ctypes.byref(chosen),
+                                                   ctypes.byref(ms)))
         return chosen.value, ms.value
 
     def delta_sizes(self, name: str) -> list:

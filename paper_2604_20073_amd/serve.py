@@ -15,9 +15,14 @@ each kind on its own relations, every request being one instance.  The loop:
   3. run one engine step (one semi-naive round for every live instance, all
      in the same launches).  The engine rejects an instance whose rows
      counted in one step exceed the per-request cap before anything is
-     written (the per-request memory bound); if a step's count passes do not
-     fit the pool at all (WCDL_E_BUDGET), the request admitted last is
-     rejected and the step is run again;
+     written (the per-request memory bound).  If a step's count passes do
+     not fit the pool at all (WCDL_E_BUDGET), the newer half of the requests
+     admitted since the last completed step (at least one; else the newest
+     request in flight) is released and set aside, and the step runs again;
+     requests set aside return to the head of the queue, to be admitted
+     again from their input, once some request completes or nothing is in
+     flight.  A request set aside ``max_deferrals`` times, or alone in the
+     engine, is rejected;
   4. requests no longer live have reached their fixpoint: record completion,
      release their rows.
 
@@ -60,7 +65,7 @@ def percentile(xs, q):
 
 class Server:
     def __init__(self, mem_budget_bytes: int = 64 << 30, max_active: int = 256, device: int = 0,
-                 instance_cap_bytes: int = 16 << 30, growth: int = 8):
+                 instance_cap_bytes: int = 16 << 30, growth: int = 8, max_deferrals: int = 3):
         self.e = Engine(device=device, batched=True, mem_budget=mem_budget_bytes,
                         instance_cap=instance_cap_bytes)
         self.stored_arity = {}
@@ -74,6 +79,7 @@ class Server:
         self.budget = mem_budget_bytes
         self.max_active = max_active
         self.growth = growth
+        self.max_deferrals = max_deferrals
 
     def close(self):
         self.e.serve_end()
@@ -99,10 +105,17 @@ class Server:
         nxt = 0
         last_bytes = 0         # resident + counted bytes reported by the last step
         admitted_allow = 0     # allowances of requests admitted since the last step
+        recent = []            # ids admitted since the last completed step, in order
+        allowance = {}         # id -> its admission allowance in bytes
+        deferred = collections.Counter()
+        aside = collections.deque()   # sent back, waiting for memory to free
         steps = 0
         t0 = time.perf_counter()
         t_note = 0.0
-        while nxt < len(trace) or queue or active:
+        while nxt < len(trace) or queue or active or aside:
+            if aside and not active:
+                queue.extendleft(reversed(aside))
+                aside.clear()
             now = time.perf_counter() - t0
             if progress and now - t_note > 10.0:
                 t_note = now
@@ -119,6 +132,8 @@ class Server:
                     break
                 queue.popleft()
                 admitted_allow += allow
+                recent.append(req["id"])
+                allowance[req["id"]] = allow
                 for name, r in facts[req["id"]].items():
                     inst = np.concatenate([np.full((len(r), 1), req["id"], np.uint32),
                                            r.astype(np.uint32)], axis=1)
@@ -139,16 +154,29 @@ class Server:
             except WcdlError as x:
                 if x.code != -8:
                     raise
-                # The step's count passes do not fit the pool: reject the
-                # request admitted last and run the step again.
-                victim = next(reversed(active))
-                active.pop(victim)
-                rejected[victim] = "pool"
-                e.serve_release([victim])
+                # The step's count passes do not fit the pool: send back the
+                # newer half of this step's admissions (or the newest request
+                # in flight) and run the step again.
+                back = recent[len(recent) // 2:] if recent else [next(reversed(active))]
+                del recent[len(recent) // 2:]
+                alone = len(active) == 1
+                e.serve_release(back)
+                requeue = []
+                for i in back:
+                    req, _ = active.pop(i)
+                    deferred[i] += 1
+                    if alone or deferred[i] > self.max_deferrals:
+                        rejected[i] = "pool"
+                    else:
+                        requeue.append(req)
+                aside.extend(requeue)
+                admitted_allow = sum(allowance[i] for i in recent)
                 if progress:
-                    progress(f"step does not fit the pool: rejected request {victim}")
+                    progress(f"step does not fit the pool: {len(requeue)} requests sent back, "
+                             f"{len(back) - len(requeue)} rejected, {len(active)} in flight")
                 continue
             steps += 1
+            recent = []
             if step_log:
                 step_log(f"step {steps} {st['wall_ms']:.1f} ms active={len(active)} "
                          f"cand={st['candidate_rows']} new={st['new_rows']} "
@@ -178,13 +206,16 @@ class Server:
                     rows[i] = {o: e.read_instance(o, i) for o in OUTPUTS[req["kind"]]}
             if finished:
                 e.serve_release(finished)
+                queue.extendleft(reversed(aside))
+                aside.clear()
         wall = time.perf_counter() - t0
         lat = list(done.values())
         return {"latency_s": done, "sizes": sizes, "rows": rows, "wall_s": wall, "steps": steps,
                 "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
                 "completed": len(done), "req_per_s": len(done) / wall if wall else None,
                 "derived": sum(sum(v.values()) for v in sizes.values()),
-                "rejected": len(rejected), "rejected_ids": rejected}
+                "rejected": len(rejected), "rejected_ids": rejected,
+                "deferrals": sum(deferred.values())}
 
 
 def replay_plain(trace: list, facts: dict, device: int = 0, instance_cap_bytes: int = 16 << 30,

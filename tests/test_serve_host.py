@@ -42,6 +42,7 @@ class FakeEngine:
         self.steps = 0
         self.last = 0           # resident + counted bytes of the last step
         self.allow = 0
+        self.since_step = {}    # admitted since the last step -> allowance
 
     def declare(self, name, k):
         self.ids[name] = len(self.ids)
@@ -59,6 +60,7 @@ class FakeEngine:
         assert inst.shape[1] == self.arity[name] + 1
         b = len(inst) * inst.shape[1] * 4
         self.allow += 8 * b
+        self.since_step[i] = 8 * b
         self.log.append(("admit", i, sorted(self.rounds_left), self.last + self.allow))
         self.rounds_left[i] = 1 + i % 4
         self.in_bytes[i] = b
@@ -85,6 +87,7 @@ class FakeEngine:
             self.out_rows[i] += 7
         self.steps += 1
         self.last, self.allow = self._resident() + bound, 0
+        self.since_step = {}
         return {"candidate_rows": 0, "new_rows": 0, "resident_rows": 0, "wall_ms": 0.0,
                 "bound_bytes": bound, "resident_bytes": self._resident(), "rejected": len(over)}
 
@@ -107,7 +110,8 @@ class FakeEngine:
 
     def serve_release(self, ids):
         for i in ids:
-            assert i not in self.released
+            assert i in self.rounds_left          # admitted and not yet released
+            self.allow -= self.since_step.pop(i, 0)
             self.released.append(i)
             self._drop(i)
 
@@ -205,13 +209,27 @@ def test_per_request_cap_rejects_and_others_complete(fake):
     assert out["completed"] == 4 and set(out["latency_s"]) == {0, 2, 3, 5}
 
 
-def test_pool_overflow_rejects_the_last_admitted(fake):
-    """A step whose count passes do not fit the pool (E_BUDGET) rejects the
-    request admitted last and runs again; nothing hangs."""
+def test_pool_overflow_sends_requests_back(fake):
+    """A step whose count passes do not fit the pool (E_BUDGET) sends the
+    newer half of its admissions back to the queue and runs again; they are
+    admitted again later and complete (nothing is rejected that fits alone,
+    nothing hangs)."""
     sizes = [50, 50, 50]
     trace, facts = trace_of(sizes)
     s = serve.Server(mem_budget_bytes=20_000, max_active=16, instance_cap_bytes=0, growth=0)
     out = s.run(trace, facts)
     s.close()
-    assert out["rejected"] >= 1 and set(out["rejected_ids"].values()) == {"pool"}
-    assert out["completed"] + out["rejected"] == 3
+    assert out["deferrals"] >= 1
+    assert out["completed"] == 3 and out["rejected"] == 0
+    e = fake[0]
+    assert sorted(set(e.released)) == [0, 1, 2]
+
+
+def test_request_over_the_pool_alone_is_rejected(fake):
+    sizes = [5, 2000, 6]
+    trace, facts = trace_of(sizes)
+    s = serve.Server(mem_budget_bytes=60_000, max_active=16, instance_cap_bytes=0, growth=0)
+    out = s.run(trace, facts)
+    s.close()
+    assert out["rejected_ids"] == {1: "pool"}
+    assert out["completed"] == 2
