@@ -971,7 +971,22 @@ Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
   {
     const DLevel& l0 = P.lvl[0];
     P.root_src = 0;
-    if (delta_atom >= 0 && l0.atom_src[delta_atom] != NONE) P.root_src = l0.atom_src[delta_atom];
+    if (delta_atom >= 0 && l0.atom_src[delta_atom] != NONE) {
+      P.root_src = l0.atom_src[delta_atom];
+    } else if ((flags & WCDL_F_COST_PLANNER) && !(e->cfg.flags & WCDL_F_BATCHED) && !e->serving) {
+      // Cost planner: enumerate the root from the source with the fewest
+      // distinct values of the root variable.
+      u64 best = ~0ull;
+      for (u32 s2 = 0; s2 < l0.nsrc; ++s2) {
+        const Atom& a = r.body[l0.src[s2].atom];
+        const std::vector<u64>& nd = relation_ndv(e, a.rel);
+        for (size_t c = 0; c < a.t.size(); ++c)
+          if (a.t[c].var && a.t[c].v == v.level_var[0] && nd[c] < best) {
+            best = nd[c];
+            P.root_src = s2;
+          }
+      }
+    }
   }
   // Sources read through a dense directory: the first column of a copy that
   // nothing has narrowed yet (no constants, no earlier variable).

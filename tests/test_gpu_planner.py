@@ -67,7 +67,11 @@ def test_planner_examines_fewer_candidates_on_a_selective_atom():
     facts = {"a": a, "b": b, "c": c}
     plain = parity(rels, rules, facts, flags=0)
     planned = parity(rels, rules, facts)
-    assert sum(planned["candidates_per_level"]) * 10 < sum(plain["candidates_per_level"])
+    # Same output rows (the last level) either way; the levels above it
+    # shrink from thousands of candidates to tens.
+    p, q = planned["candidates_per_level"], plain["candidates_per_level"]
+    assert p[0] == len(c) and p[2] == q[2]
+    assert (p[0] + p[1]) * 50 < q[0] + q[1]
 
 
 def test_autotune_points_chooses_and_remembers():
