@@ -495,7 +495,8 @@ def bench_serve(args):
         small = [r["id"] for r in trace if r["m"] <= 20_000 and r["id"] >= args.warm]
         check = set(g.choice(small, size=min(24, len(small)), replace=False).tolist())
         cap, pool = int(args.cap_gib * (1 << 30)), int(args.pool_gib * (1 << 30))
-        srv = Server(mem_budget_bytes=pool, instance_cap_bytes=cap, max_active=args.max_active)
+        srv = Server(mem_budget_bytes=pool, instance_cap_bytes=cap, max_active=args.max_active,
+                     solo_rows=int(args.solo_rows))
         slog = None
         if args.step_log:
             fh = open(args.step_log, "w", buffering=1)
@@ -551,10 +552,12 @@ def bench_serve(args):
            "config": {"workload": (f"served: {args.requests} requests after {args.warm} warm-up, "
                                    f"Poisson {args.rate}/s, m log-uniform [1e3, {args.m_max:.0e}], "
                                    "tc/tri/c4/pt on ER or R-MAT"),
-                      "pool_gib": args.pool_gib, "cap_gib": args.cap_gib},
+                      "pool_gib": args.pool_gib, "cap_gib": args.cap_gib,
+                      "solo_rows": int(args.solo_rows)},
            "served": {"p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "completed": len(keep),
                       "rejected": served["rejected"], "req_per_s": per_s(served["completed"], sw),
-                      "wall_s": round(sw, 2), "steps": served["steps"],
+                      "wall_s": round(sw, 2), "steps": served["steps"], "alone": served.get("solo", 0),
+                      "sent_back": served.get("deferrals", 0),
                       "tuples_per_s": per_s(served["derived"], sw)},
            "plain_fifo": {"p50_s": pct(plat, 50), "p99_s": pct(plat, 99), "completed": len(plat),
                           "rejected": plain["rejected"],
@@ -600,6 +603,8 @@ def main():
     ap.add_argument("--max-active", type=int, default=256)
     ap.add_argument("--step-log", default="", help="serve: write a line per admission and step here")
     ap.add_argument("--legs", default="served,plain", help="serve: which of served,plain to run")
+    ap.add_argument("--solo-rows", type=float, default=1e5,
+                    help="serve: requests with at least this many input rows run alone between steps")
     ap.add_argument("--plain-deadline", type=float, default=0.0,
                     help="serve: start no plain request after this many seconds (0: none)")
     ap.add_argument("--sizes-out", default="", help="serve: write per-request result sizes here")

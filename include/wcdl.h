@@ -98,11 +98,15 @@ typedef int32_t wcdl_status;
 #define WCDL_F_COST_PLANNER 0x400u /* choose each rule version's variable order
                                     by a cost model over per-column distinct
                                     counts of the body relations (the paper's
-                                    future work on variable orders, Sec. 9)
-                                    instead of the structural heuristic (most
-                                    shared variable first, delta-first); rules
-                                    with a user order, batched engines and
-                                    serving keep theirs */
+                                    future work on variable orders, Sec. 9):
+                                    the structural heuristic's order (most
+                                    shared variable first, delta-first) is
+                                    replaced where the model predicts a lower
+                                    total with under a quarter of its join
+                                    work, and a join without a
+                                    delta is rooted at its most selective
+                                    source; rules with a user order, batched
+                                    engines and serving keep theirs */
 #define WCDL_F_BATCHED 0x10u     /* batched mode: the engine holds many independent
                                     instances of one program.  Every relation gets
                                     an implicit leading column, the instance id:
@@ -379,6 +383,12 @@ wcdl_status wcdl_read_rows(const wcdl_engine* e, uint32_t rel, uint64_t first, u
  * hold the last candidate's (identical) results afterwards. */
 wcdl_status wcdl_autotune(wcdl_engine* e, const uint32_t* wg_per_cu, uint32_t n, uint32_t* chosen,
                           double* best_ms);
+
+/* Return the device blocks the engine keeps cached for reuse (freed
+ * scratch) to the allocator, so that other engines or the caller can use
+ * that memory; relations are untouched.  Waits for the engine's streams.
+ * *released (may be NULL) receives the bytes returned. */
+wcdl_status wcdl_trim(wcdl_engine* e, uint64_t* released);
 
 /* Strategy flags the configuration tuner may set or clear. */
 #define WCDL_TUNE_FLAGS (WCDL_F_STREAMS_OFF | WCDL_F_XPROD_OFF | WCDL_F_STAGE_OFF | \

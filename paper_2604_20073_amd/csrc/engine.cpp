@@ -691,8 +691,10 @@ const std::vector<u64>& relation_ndv(Engine* e, u32 rel) {
   return slot.second;
 }
 
-double order_cost(Engine* e, const Rule& r, int delta_atom, const std::vector<u32>& order,
-                  const std::vector<std::vector<u64>>& ndv, const std::vector<double>& rows) {
+// Estimated (join work, output sort work) of an order.
+std::pair<double, double> order_cost(const Rule& r, int delta_atom, const std::vector<u32>& order,
+                                     const std::vector<std::vector<u64>>& ndv,
+                                     const std::vector<double>& rows) {
   const u32 nv = r.nvars;
   std::vector<bool> bound(nv, false);
   // Domain estimate per variable: the most distinct values any atom has for it.
@@ -738,12 +740,15 @@ double order_cost(Engine* e, const Rule& r, int delta_atom, const std::vector<u3
   const size_t hk = r.head.t.size();
   const double sort_cost = delta_atom < 0 && prefix == hk && hk == order.size() ? 0.0
                            : prefix + 1 >= hk ? 1.0 : 6.0;
-  (void)e;
-  return cost + n * sort_cost;
+  return {cost, n * sort_cost};
 }
 
-// Lowest-cost connected order, or empty when no statistics apply.
-std::vector<u32> cost_order(Engine* e, const Rule& r, int delta_atom) {
+// Lowest-cost connected order; the incumbent (the heuristic's order) is kept
+// unless the estimate's total is lower and its join work below a quarter of
+// the incumbent's: independence estimates miss skew (hub-heavy graphs), so
+// only a large predicted gain overrides the structural choice.
+std::vector<u32> cost_order(Engine* e, const Rule& r, int delta_atom,
+                            const std::vector<u32>& incumbent) {
   std::vector<std::vector<u64>> ndv;
   std::vector<double> rows;
   for (size_t a = 0; a < r.body.size(); ++a) {
@@ -765,7 +770,7 @@ std::vector<u32> cost_order(Engine* e, const Rule& r, int delta_atom) {
     roots = vars;
   }
   std::vector<u32> best, cur;
-  double best_cost = std::numeric_limits<double>::infinity();
+  double best_cost = std::numeric_limits<double>::infinity(), best_join = 0;
   std::vector<bool> used(r.nvars, false);
   auto connected = [&](u32 w) {  // w shares an atom with a bound variable
     for (auto& a : r.body) {
@@ -781,8 +786,8 @@ std::vector<u32> cost_order(Engine* e, const Rule& r, int delta_atom) {
   };
   std::function<void()> dfs = [&] {
     if (cur.size() == vars.size()) {
-      const double c = order_cost(e, r, delta_atom, cur, ndv, rows);
-      if (c < best_cost) best_cost = c, best = cur;
+      const auto c = order_cost(r, delta_atom, cur, ndv, rows);
+      if (c.first + c.second < best_cost) best_cost = c.first + c.second, best_join = c.first, best = cur;
       return;
     }
     for (u32 v : (cur.empty() ? roots : vars)) {
@@ -802,6 +807,10 @@ std::vector<u32> cost_order(Engine* e, const Rule& r, int delta_atom) {
     }
   };
   dfs();
+  if (incumbent.size() == vars.size()) {
+    const auto inc = order_cost(r, delta_atom, incumbent, ndv, rows);
+    if (!(best_cost < inc.first + inc.second && best_join * 4.0 < inc.first)) return incumbent;
+  }
   return best;
 }
 
@@ -816,7 +825,7 @@ Version plan_version(Engine* e, u32 ri, int delta_atom, u32 flags) {
   v.level_var = choose_order(r, delta_atom);
   if ((flags & WCDL_F_COST_PLANNER) && r.var_order.empty() && !(e->cfg.flags & WCDL_F_BATCHED) &&
       !e->serving) {
-    std::vector<u32> o = cost_order(e, r, delta_atom);
+    std::vector<u32> o = cost_order(e, r, delta_atom, v.level_var);
     if (o.size() == v.level_var.size()) v.level_var = std::move(o);
   }
   const u32 m = (u32)v.level_var.size();
@@ -2766,6 +2775,7 @@ wcdl_status wcdl_clear_relation(wcdl_engine* e, uint32_t rel) {
     Relation& R = e->rels[rel];
     R.base = empty_cols(R.arity, canonical(R.arity));
     R.full = empty_cols(R.arity, canonical(R.arity));
+    R.head = empty_cols(R.arity, canonical(R.arity));
     R.full_ord.clear();
     R.delta_ord.clear();
   });
@@ -3108,6 +3118,15 @@ wcdl_status wcdl_autotune(wcdl_engine* e, const uint32_t* wg_per_cu, uint32_t n,
     e->cfg.wg_per_cu = best;
     if (chosen) *chosen = best;
     if (best_ms) *best_ms = bt;
+  });
+}
+
+wcdl_status wcdl_trim(wcdl_engine* e, uint64_t* released) {
+  return guarded(e, [&] {
+    sync_all(e);
+    const u64 n = e->mem->cached_bytes();
+    e->mem->release_cached();
+    if (released) *released = n;
   });
 }
 

@@ -56,6 +56,11 @@ class DeviceMemory {
   void sync_point();  // pending frees become reusable
   void release_cached();
   size_t live_bytes() const { return live_bytes_; }
+  size_t cached_bytes() const {
+    size_t n = 0;
+    for (auto& b : free_) n += b.first;
+    return n;
+  }
 
  private:
   static size_t size_class(size_t bytes);

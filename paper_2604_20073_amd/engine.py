@@ -115,7 +115,7 @@ EXPORTS = [
     "wcdl_binary_plan", "wcdl_run",
     "wcdl_relation_size", "wcdl_read_columns", "wcdl_delta_sizes", "wcdl_work_slice",
     "wcdl_owner_key", "wcdl_decode_unit", "wcdl_relation_range", "wcdl_read_rows",
-    "wcdl_autotune", "wcdl_autotune_points", "wcdl_serve_begin", "wcdl_serve_admit", "wcdl_serve_step",
+    "wcdl_autotune", "wcdl_autotune_points", "wcdl_trim", "wcdl_serve_begin", "wcdl_serve_admit", "wcdl_serve_step",
     "wcdl_serve_live", "wcdl_serve_release", "wcdl_serve_end",
     "wcdl_instance_create", "wcdl_instance_id", "wcdl_instance_load", "wcdl_instance_size",
     "wcdl_instance_read", "wcdl_instance_destroy", "wcdl_run_batch", "wcdl_step",
@@ -159,6 +159,7 @@ def lib():
     L.wcdl_autotune_points.argtypes = [P, ctypes.POINTER(_TunePoint), u32, pu32,
                                        ctypes.POINTER(ctypes.c_double)]
     L.wcdl_binary_plan.argtypes = [P, pu32]
+    L.wcdl_trim.argtypes = [P, pu64]
     L.wcdl_run.argtypes = [P, ctypes.POINTER(_Stats)]
     L.wcdl_relation_size.argtypes = [P, u32, pu64]
     L.wcdl_read_columns.argtypes = [P, u32, ctypes.POINTER(P), u64, pu64, ctypes.c_int]
@@ -535,6 +536,12 @@ class Engine:
         self._check(self._lib.wcdl_autotune(self._e, c, len(wg_per_cu), ctypes.byref(chosen),
                                             ctypes.byref(ms)))
         return chosen.value, ms.value
+
+    def trim(self) -> int:
+        """Return the engine's cached free device blocks; bytes returned."""
+        n = ctypes.c_uint64()
+        self._check(self._lib.wcdl_trim(self._e, ctypes.byref(n)))
+        return n.value
 
     def autotune_points(self, points):
         """Run the program once per configuration point, a (wg_per_cu,

@@ -18,13 +18,21 @@ each kind on its own relations, every request being one instance.  The loop:
      written (the per-request memory bound).  If a step's count passes do
      not fit the pool at all (WCDL_E_BUDGET), the newer half of the requests
      admitted since the last completed step (at least one; else the newest
-     request in flight) is released and set aside, and the step runs again;
+     quarter of the requests in flight, at least one) is released and set
+     aside, and the step runs again;
      requests set aside return to the head of the queue, to be admitted
      again from their input, once some request completes or nothing is in
      flight.  A request set aside ``max_deferrals`` times, or alone in the
      engine, is rejected;
   4. requests no longer live have reached their fixpoint: record completion,
      release their rows.
+
+Requests whose input has at least ``solo_rows`` rows do not join the shared
+steps: one such request at a time runs alone on a plain engine of its kind
+(with the per-request cap as its memory budget) between two steps.  In a
+shared step every instance waits for the slowest one, so a few very large
+requests would otherwise hold up every small one, and their rows would crowd
+the pool.
 
 Every evaluation step runs in the engine's kernels; this module only decides
 when to admit, step and release.  `replay_plain` serves the same trace first
@@ -65,9 +73,14 @@ def percentile(xs, q):
 
 class Server:
     def __init__(self, mem_budget_bytes: int = 64 << 30, max_active: int = 256, device: int = 0,
-                 instance_cap_bytes: int = 16 << 30, growth: int = 8, max_deferrals: int = 3):
+                 instance_cap_bytes: int = 16 << 30, growth: int = 8, max_deferrals: int = 3,
+                 solo_rows: int = 100_000):
         self.e = Engine(device=device, batched=True, mem_budget=mem_budget_bytes,
                         instance_cap=instance_cap_bytes)
+        self.device = device
+        self.cap = instance_cap_bytes
+        self.solo_rows = solo_rows
+        self.solo_engines = {}
         self.stored_arity = {}
         for rels, _ in PROGRAMS.values():
             for name, k in rels.items():
@@ -84,6 +97,40 @@ class Server:
     def close(self):
         self.e.serve_end()
         self.e.close()
+        for e in self.solo_engines.values():
+            e.close()
+
+    def _run_solo(self, req, facts, keep):
+        """Run one request alone on the plain engine of its kind; afterwards
+        its relations are cleared and its cached scratch returned, so none of
+        its memory stays held beside the shared engine.  Returns its output
+        sizes and (if keep) rows, or None when it exceeds the cap (or finds
+        no device memory left)."""
+        kind = req["kind"]
+        e = self.solo_engines.get(kind)
+        if e is None:
+            e = Engine(device=self.device, mem_budget=self.cap)
+            rels, rules = PROGRAMS[kind]
+            for name, k in rels.items():
+                e.declare(name, k)
+            e.add_rules(rules)
+            self.solo_engines[kind] = e
+        self.e.trim()   # the shared engine's cached scratch, for this run
+        try:
+            for name, r in facts.items():
+                e.load(name, r)
+            try:
+                e.run()
+            except WcdlError as x:
+                if x.code not in (-7, -8):
+                    raise
+                return None
+            return ({o: e.size(o) for o in OUTPUTS[kind]},
+                    {o: e.read_numpy(o) for o in OUTPUTS[kind]} if keep else None)
+        finally:
+            for name in PROGRAMS[kind][0]:
+                e.clear(name)
+            e.trim()
 
     def input_bytes(self, req_facts: dict) -> int:
         return sum(len(r) * self.stored_arity[name] * 4 for name, r in req_facts.items())
@@ -109,10 +156,12 @@ class Server:
         allowance = {}         # id -> its admission allowance in bytes
         deferred = collections.Counter()
         aside = collections.deque()   # sent back, waiting for memory to free
+        solo = collections.deque()    # large requests, run alone between steps
+        n_solo = 0
         steps = 0
         t0 = time.perf_counter()
         t_note = 0.0
-        while nxt < len(trace) or queue or active or aside:
+        while nxt < len(trace) or queue or active or aside or solo:
             if aside and not active:
                 queue.extendleft(reversed(aside))
                 aside.clear()
@@ -127,6 +176,9 @@ class Server:
             # Admission by the memory bound of the last count pass.
             while queue and len(active) < self.max_active:
                 req = queue[0]
+                if self.solo_rows and sum(len(r) for r in facts[req["id"]].values()) >= self.solo_rows:
+                    solo.append(queue.popleft())
+                    continue
                 allow = self.growth * self.input_bytes(facts[req["id"]])
                 if active and last_bytes + admitted_allow + allow > self.budget:
                     break
@@ -145,8 +197,24 @@ class Server:
                 if progress and req.get("m", 0) >= 1_000_000:
                     progress(f"admitted request {req['id']} ({req['kind']}, m={req['m']}) with "
                              f"{len(active)} active")
+            if solo:
+                # One large request alone, between two shared steps.
+                req = solo.popleft()
+                n_solo += 1
+                keep = keep_results or req["id"] in keep_ids
+                res = self._run_solo(req, facts[req["id"]], keep)
+                if res is None:
+                    rejected[req["id"]] = "cap"
+                else:
+                    done[req["id"]] = time.perf_counter() - t0 - req["arrival"]
+                    sizes[req["id"]] = res[0]
+                    if keep:
+                        rows[req["id"]] = res[1]
+                if step_log:
+                    step_log(f"solo {req['id']} {req['kind']} m={req.get('m')} "
+                             f"{'rejected' if res is None else 'done'}")
             if not active:
-                if nxt < len(trace):
+                if nxt < len(trace) and not solo:
                     time.sleep(max(0.0, min(0.01, trace[nxt]["arrival"] - now)))
                 continue
             try:
@@ -157,7 +225,11 @@ class Server:
                 # The step's count passes do not fit the pool: send back the
                 # newer half of this step's admissions (or the newest request
                 # in flight) and run the step again.
-                back = recent[len(recent) // 2:] if recent else [next(reversed(active))]
+                if recent:
+                    back = recent[len(recent) // 2:]
+                else:
+                    ids = list(active)
+                    back = ids[len(ids) - max(1, len(ids) // 4):]
                 del recent[len(recent) // 2:]
                 alone = len(active) == 1
                 e.serve_release(back)
@@ -215,14 +287,16 @@ class Server:
                 "completed": len(done), "req_per_s": len(done) / wall if wall else None,
                 "derived": sum(sum(v.values()) for v in sizes.values()),
                 "rejected": len(rejected), "rejected_ids": rejected,
-                "deferrals": sum(deferred.values())}
+                "deferrals": sum(deferred.values()), "solo": n_solo}
 
 
 def replay_plain(trace: list, facts: dict, device: int = 0, instance_cap_bytes: int = 16 << 30,
                  progress=None, deadline_s: float = 0.0) -> dict:
     """The same trace, first come first served, one request at a time, each
     on a plain engine running its kind's program; a request whose run
-    exceeds the per-request cap (WCDL_E_BUDGET) is rejected.  With a
+    exceeds the per-request cap (WCDL_E_BUDGET) is rejected.  A run out of
+    device memory is run once more after every engine returns its cached
+    scratch; if that fails too, the error is raised.  With a
     deadline, no request is started after it (those left are reported as
     not reached)."""
     engines = {}
@@ -247,15 +321,26 @@ def replay_plain(trace: list, facts: dict, device: int = 0, instance_cap_bytes: 
         if req["arrival"] > now:
             time.sleep(req["arrival"] - now)
         e = engines[req["kind"]]
-        for name in PROGRAMS[req["kind"]][0]:
-            e.clear(name)
-        for name, r in facts[req["id"]].items():
-            e.load(name, r)
-        try:
-            e.run()
-        except WcdlError as x:
-            if x.code != -8:
-                raise
+        ok = False
+        for attempt in range(2):
+            for name in PROGRAMS[req["kind"]][0]:
+                e.clear(name)
+            try:
+                for name, r in facts[req["id"]].items():
+                    e.load(name, r)
+                e.run()
+                ok = True
+                break
+            except WcdlError as x:
+                if x.code == -8:
+                    break
+                if x.code != -7 or attempt:
+                    raise
+                # Out of device memory: the other engines' cached scratch
+                # goes back first, then the request runs once more.
+                for other in engines.values():
+                    other.trim()
+        if not ok:
             rejected.append(req["id"])
             continue
         done[req["id"]] = time.perf_counter() - t0 - req["arrival"]

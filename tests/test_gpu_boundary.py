@@ -251,3 +251,21 @@ def test_budget_stops_the_count_pass_early():
                                 {"edge": small})
     assert np.array_equal(e.read_numpy("c"), expect["c"])
     e.close()
+
+
+def test_trim_returns_cached_blocks_and_keeps_relations():
+    edges = W.er_graph(700, 3000, 94)
+    rels = {"edge": 2, "path": 2}
+    _, expect = oracle.evaluate(rels, TC, {"edge": edges})
+    e = Engine()
+    for n, k in rels.items():
+        e.declare(n, k)
+    e.add_rules(TC)
+    e.load("edge", edges)
+    e.run()
+    assert e.trim() > 0                   # a run leaves freed scratch cached
+    assert e.trim() == 0
+    assert np.array_equal(e.read_numpy("path"), expect["path"])
+    e.run()
+    assert np.array_equal(e.read_numpy("path"), expect["path"])
+    e.close()

@@ -28,7 +28,8 @@ class FakeEngine:
     whose bytes do not fit `mem_budget` raises E_BUDGET."""
 
     def __init__(self, device=0, batched=True, mem_budget=0, instance_cap=0):
-        assert batched
+        self.batched = batched
+        self.loaded = 0          # plain mode: rows loaded since the last clear
         self.arity = {}
         self.ids = {}
         self.budget, self.cap = mem_budget, instance_cap
@@ -90,6 +91,28 @@ class FakeEngine:
         self.since_step = {}
         return {"candidate_rows": 0, "new_rows": 0, "resident_rows": 0, "wall_ms": 0.0,
                 "bound_bytes": bound, "resident_bytes": self._resident(), "rejected": len(over)}
+
+    # Plain mode (a request run alone): 3 output rows per input row; the run
+    # fails with E_BUDGET when those rows exceed the budget.
+    def clear(self, name):
+        self.loaded = 0
+
+    def load(self, name, rows):
+        self.loaded += len(rows)
+
+    def run(self):
+        if self.budget and self.loaded * 3 * 8 > self.budget:
+            raise WcdlError(-8, "over budget")
+        return {}
+
+    def size(self, name):
+        return 3 * self.loaded
+
+    def read_numpy(self, name):
+        return np.zeros((3 * self.loaded, 2), np.uint32)
+
+    def trim(self):
+        return 0
 
     def serve_rejected(self):
         return sorted(self.rejected)
@@ -233,3 +256,21 @@ def test_request_over_the_pool_alone_is_rejected(fake):
     s.close()
     assert out["rejected_ids"] == {1: "pool"}
     assert out["completed"] == 2
+
+
+def test_large_requests_run_alone_between_steps(fake):
+    """Requests with at least solo_rows input rows run alone on plain
+    engines (one per kind) between shared steps; one over the cap there is
+    rejected; the small ones are served in shared steps as before."""
+    sizes = [5, 300, 6, 20000, 7]
+    trace, facts = trace_of(sizes)
+    s = serve.Server(mem_budget_bytes=1 << 40, max_active=16, instance_cap_bytes=100_000,
+                     solo_rows=200)
+    out = s.run(trace, facts, keep_ids={1})
+    s.close()
+    assert out["solo"] == 2
+    assert out["rejected_ids"] == {3: "cap"}
+    assert out["completed"] == 4 and out["sizes"][1] == {"path": 900}
+    assert out["rows"][1]["path"].shape == (900, 2)
+    batched = fake[0]
+    assert sorted(set(batched.released)) == [0, 2, 4]     # only the small ones shared steps
