@@ -174,6 +174,13 @@ typedef struct {
                                 and subtracted before the next is written (0 =
                                 6 % of device memory).  Fails with WCDL_E_BUDGET
                                 if one work unit alone produces more. */
+  uint32_t head_ratio;       /* a relation's head run (Sec. 4, Merge) is merged
+                                into its body once it holds more than
+                                1/head_ratio of the body's rows (and 65,536
+                                rows); 0 = default 8 */
+  uint32_t bitmap_min_run;   /* shortest run (rows sharing all but the last
+                                column) that gets a run bitmap for leaf probes;
+                                0 = default 512, smaller values act as 512 */
 } wcdl_config;
 
 /* Fill `cfg` with defaults (device 0, own streams, hipMalloc, no budget). */
@@ -396,12 +403,15 @@ wcdl_status wcdl_trim(wcdl_engine* e, uint64_t* released);
                          WCDL_F_GROUPED_SORT_OFF | WCDL_F_COST_PLANNER)
 
 /* One configuration for wcdl_autotune_points: the partition granularity, the
- * count-pass staging arena size (0 = default) and the strategy flags (only
- * bits of WCDL_TUNE_FLAGS; the engine's other flags are kept). */
+ * count-pass staging arena size (0 = default), the strategy flags (only bits
+ * of WCDL_TUNE_FLAGS; the engine's other flags are kept), the head-run flush
+ * ratio and the run-bitmap threshold. */
 typedef struct {
   uint32_t wg_per_cu;
   uint32_t stage_pct;
   uint32_t flags;
+  uint32_t head_ratio;       /* as in wcdl_config (0 = default) */
+  uint32_t bitmap_min_run;   /* as in wcdl_config (0 = default) */
 } wcdl_tune_point;
 
 /* Configuration tuner: run the program once per point, keep the fastest

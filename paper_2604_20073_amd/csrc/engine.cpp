@@ -1255,10 +1255,10 @@ void ensure_directory(Engine* e, Cols& c) {
 
 // Run bitmaps of a copy that leaf levels probe (see Cols).  Built once per
 // copy; only for copies that stay unchanged while they are read.
-constexpr u32 RUN_BITMAP_MIN = 512;
+u32 run_bitmap_min(const Engine* e) { return e->cfg.bitmap_min_run ? e->cfg.bitmap_min_run : 512u; }
 
 void ensure_run_bitmaps(Engine* e, Cols& c) {
-  if (c.bm_tried || c.n < RUN_BITMAP_MIN || c.arity() < 2) return;
+  if (c.bm_tried || c.n < run_bitmap_min(e) || c.arity() < 2) return;
   c.bm_tried = true;
   const u32 k = c.arity();
   // Upper bound of the last column: the OR of its values.
@@ -1273,7 +1273,7 @@ void ensure_run_bitmaps(Engine* e, Cols& c) {
   WCDL_HIP(hipMemGetInfo(&free_b, &total_b));
   const u64 budget = std::min<u64>((u64)(total_b * 0.02), (u64)(free_b / 8));
   auto cp = c.ptrs();
-  c.bm_min = build_run_bitmaps(ctx(e), k, cp.data(), c.n, vmax, RUN_BITMAP_MIN, budget, &c.bm_at,
+  c.bm_min = build_run_bitmaps(ctx(e), k, cp.data(), c.n, vmax, run_bitmap_min(e), budget, &c.bm_at,
                                &c.bm, &c.bm_words);
 }
 
@@ -1322,7 +1322,8 @@ struct VRun {
   u64 stage_chunks = 0, used_chunks = 0;
   std::vector<u32> overflowed;
   DBuf<u32> d_overflowed;
-  DBuf<u64> scal;  // [0] K, [1] T, [2] total, [3] materialize error flag
+  u64* scal = nullptr;  // [0] K, [1] T, [2] total, [3] materialize error flag
+                        // (4 words of the batch's scalar array)
   u64 K = 0, T = 0, total = 0;
   u64 out_off = 0;
   RootSpace rs{};
@@ -1371,7 +1372,7 @@ void repartition(Engine* e, VRun& R, u64 max_rows, Stats& st) {
     R.offsets = DBuf<u64>(c.mem, np);
     auto t = Clock::now();
     join_run(c, R.d_plan.get(), R.rs, R.part, R.v->lds_bytes, 0, R.counts.get(), nullptr, 0, np);
-    scan_u64_excl(c, R.counts.get(), R.offsets.get(), np, R.scal.get() + 2);
+    scan_u64_excl(c, R.counts.get(), R.offsets.get(), np, R.scal + 2);
     recycle(e);
     st.phase[WCDL_PH_COUNT] += ms_since(t);
   }
@@ -1497,6 +1498,15 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     fill_u32(ctx(e), abort_flag.get(), 1, 0);
   }
   const u64 held0 = bounded ? resident_bytes(e) : 0;
+  // Every version's scalars (K, T, total, error flag) in one array, read back
+  // with one copy per phase instead of one per version.
+  DBuf<u64> scal_all(e->mem.get(), 4 * runs.size());
+  fill_u64(ctx(e), scal_all.get(), 4 * runs.size(), 0);
+  std::vector<u64> hscal(4 * runs.size());
+  auto read_scalars = [&] {
+    WCDL_HIP(hipMemcpy(hscal.data(), scal_all.get(), hscal.size() * sizeof(u64), hipMemcpyDeviceToHost));
+  };
+  auto scalar_of = [&](const VRun& R, int k) { return hscal[(size_t)(R.scal - scal_all.get()) + k]; };
   WCDL_HIP(hipStreamSynchronize(e->streams[0]));
   // ---- Phase A: plan upload, constant narrowing, root-key flags.
   for (size_t i = 0; i < vs.size(); ++i) {
@@ -1521,21 +1531,21 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     R.d_plan = DBuf<DPlan>(c.mem, 1);
     WCDL_HIP(hipMemcpyAsync(R.d_plan.get(), R.host_plan, sizeof(DPlan), hipMemcpyHostToDevice, c.s));
     R.rng0 = DBuf<u32>(c.mem, 2 * MAXN);
-    R.scal = DBuf<u64>(c.mem, 4);
-    fill_u64(c, R.scal.get(), 4, 0);
+    R.scal = scal_all.get() + 4 * i;
     join_init_ranges(c, R.d_plan.get(), P.natoms, R.rng0.get());
     const u32 n = P.atom_n[R.root_atom];
     R.flags = DBuf<u32>(c.mem, n);
     R.pos = DBuf<u64>(c.mem, n);
     join_root_flags(c, P.atom_col[R.root_atom][R.root_pos], R.rng0.get(), R.root_atom, n,
-                    R.flags.get(), R.pos.get(), R.scal.get());
+                    R.flags.get(), R.pos.get(), R.scal);
   }
   sync_all(e);
+  read_scalars();
   // ---- Phase B: root keys, histogram, prefix sums.
   for (auto& R : runs) {
     if (R.skip) continue;
     Ctx c = ctx(e, R.si);
-    WCDL_HIP(hipMemcpy(&R.K, R.scal.get(), sizeof(u64), hipMemcpyDeviceToHost));
+    R.K = scalar_of(R, 0);
     if (R.K == 0) { R.skip = true; continue; }
     const DPlan& P = R.v->plan;
     const u32 n = P.atom_n[R.root_atom];
@@ -1554,9 +1564,10 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     join_histogram(c, R.d_plan.get(), R.rs, R.W.get(), P.xprod ? R.klo.get() : nullptr,
                    P.xprod ? R.kd.get() : nullptr, P.m);
     R.t_hist.stop(c.s);
-    scan_u64_incl(c, R.W.get(), R.C.get(), R.K, R.scal.get() + 1);
+    scan_u64_incl(c, R.W.get(), R.C.get(), R.K, R.scal + 1);
   }
   sync_all(e);
+  read_scalars();
   st.phase[WCDL_PH_HISTOGRAM] += ms_since(t_hist);
   // ---- Phase C: count pass (Alg. 1 Phase 2) and offsets.
   auto t_count = Clock::now();
@@ -1569,7 +1580,7 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     u64 want_total = 0;
     for (auto& R : runs) {
       if (R.skip || R.v->plan.xprod) continue;
-      WCDL_HIP(hipMemcpy(&R.T, R.scal.get() + 1, sizeof(u64), hipMemcpyDeviceToHost));
+      R.T = scalar_of(R, 1);
       auto rit = e->rows_per_unit.find(std::make_pair(R.v->rule, R.v->delta_atom));
       if (R.T == 0 || rit == e->rows_per_unit.end()) continue;
       const u64 wpc = e->cfg.wg_per_cu ? e->cfg.wg_per_cu : 32;
@@ -1592,7 +1603,7 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
   }
   for (auto& R : runs) {
     if (R.skip) continue;
-    WCDL_HIP(hipMemcpy(&R.T, R.scal.get() + 1, sizeof(u64), hipMemcpyDeviceToHost));
+    R.T = scalar_of(R, 1);
     if (R.T == 0) { R.skip = true; continue; }
     R.rs.T = R.T;
     st.units += R.T;
@@ -1653,12 +1664,13 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     join_run(c, R.d_plan.get(), R.rs, R.part, R.v->lds_bytes, R.staged ? 2 : 0, R.counts.get(),
              nullptr, 0, p);
     R.t_count.stop(c.s);
-    scan_u64_excl(c, R.counts.get(), R.offsets.get(), p, R.scal.get() + 2);
+    scan_u64_excl(c, R.counts.get(), R.offsets.get(), p, R.scal + 2);
   }
   sync_all(e);
+  read_scalars();
   for (auto& R : runs) {
     if (R.skip || R.v->plan.xprod) continue;
-    WCDL_HIP(hipMemcpy(&R.total, R.scal.get() + 2, sizeof(u64), hipMemcpyDeviceToHost));
+    R.total = scalar_of(R, 2);
     e->rows_per_unit[std::make_pair(R.v->rule, R.v->delta_atom)] = (double)R.total / (double)R.T;
     if (R.staged) {
       WCDL_HIP(hipMemcpy(&R.used_chunks, R.stage_next.get(), sizeof(u64), hipMemcpyDeviceToHost));
@@ -1756,7 +1768,7 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
     DPlan& P = R.v->plan;
     for (u32 h = 0; h < P.head_arity; ++h) P.out[h] = base[h] - lo_row;
     P.out_rows = hi_row;
-    P.err = reinterpret_cast<u32*>(R.scal.get() + 3);
+    P.err = reinterpret_cast<u32*>(R.scal + 3);
     if (R.staged) {
       P.cand = nullptr;  // counted in the staged count pass
     } else {
@@ -1799,7 +1811,7 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
   };
   auto check_flag = [&](VRun& R) {
     u64 flag = 0;
-    WCDL_HIP(hipMemcpy(&flag, R.scal.get() + 3, sizeof(u64), hipMemcpyDeviceToHost));
+    WCDL_HIP(hipMemcpy(&flag, R.scal + 3, sizeof(u64), hipMemcpyDeviceToHost));
     if (flag) throw Error(WCDL_E_DEVICE, "internal error: materialize produced more rows than counted");
   };
   // ---- Phase D: materialize (Alg. 1 Phase 3), whole heads, phase-aligned.
@@ -2007,8 +2019,8 @@ void flush_head(Engine* e, u32 rel, Stats* st) {
   if (st) st->phase[WCDL_PH_MERGE] += ms_since(t);
 }
 
-// Head runs are flushed once they hold more than this share of the body.
-constexpr u64 HEAD_RATIO = 8;
+// Head runs are flushed once they hold more than 1/ratio of the body.
+u64 head_ratio(const Engine* e) { return e->cfg.head_ratio ? e->cfg.head_ratio : 8u; }
 constexpr u64 HEAD_MIN_ROWS = 1u << 16;
 
 // Merge the new rows into the relation (Merge, Sec. 4).  With `use_head`
@@ -2060,7 +2072,7 @@ void commit_delta(Engine* e, u32 rel, Cols& d, Stats& st, bool consume = false,
     WCDL_HIP(hipStreamSynchronize(e->streams[0]));
     st.phase[WCDL_PH_MERGE] += ms_since(t);
     if (checked(e)) check_sorted(e, R.head, "the head run", rel);
-    if (R.head.n > std::max<u64>(HEAD_MIN_ROWS, R.full.n / HEAD_RATIO)) flush_head(e, rel, &st);
+    if (R.head.n > std::max<u64>(HEAD_MIN_ROWS, R.full.n / head_ratio(e))) flush_head(e, rel, &st);
     return;
   }
   if (d.n) {
@@ -3151,12 +3163,15 @@ wcdl_status wcdl_autotune_points(wcdl_engine* e, const wcdl_tune_point* points, 
     key += "#" + std::to_string(bucket) + "#";
     for (u32 i = 0; i < n; ++i)
       key += std::to_string(points[i].wg_per_cu) + "," + std::to_string(points[i].stage_pct) + "," +
-             std::to_string(points[i].flags) + ";";
+             std::to_string(points[i].flags) + "," + std::to_string(points[i].head_ratio) + "," +
+             std::to_string(points[i].bitmap_min_run) + ";";
     const u32 keep = e->cfg.flags & ~(u32)WCDL_TUNE_FLAGS;
     auto apply = [&](const wcdl_tune_point& p) {
       e->cfg.wg_per_cu = p.wg_per_cu;
       e->cfg.stage_pct = p.stage_pct;
       e->cfg.flags = keep | p.flags;
+      e->cfg.head_ratio = p.head_ratio;
+      e->cfg.bitmap_min_run = p.bitmap_min_run;
     };
     auto hit = tune_memo().find(key);
     if (hit != tune_memo().end()) {

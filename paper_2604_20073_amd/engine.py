@@ -53,7 +53,8 @@ class _Config(ctypes.Structure):
                 ("streams", ctypes.POINTER(ctypes.c_void_p)), ("alloc", _Allocator),
                 ("mem_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("wg_per_cu", ctypes.c_uint32), ("stage_pct", ctypes.c_uint32),
-                ("instance_cap_bytes", ctypes.c_uint64), ("chunk_bytes", ctypes.c_uint64)]
+                ("instance_cap_bytes", ctypes.c_uint64), ("chunk_bytes", ctypes.c_uint64),
+                ("head_ratio", ctypes.c_uint32), ("bitmap_min_run", ctypes.c_uint32)]
 
 
 class _Stats(ctypes.Structure):
@@ -74,7 +75,8 @@ class _StepStats(ctypes.Structure):
 
 class _TunePoint(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_uint32), ("stage_pct", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("head_ratio", ctypes.c_uint32),
+                ("bitmap_min_run", ctypes.c_uint32)]
 
 
 class _Term(ctypes.Structure):
@@ -213,7 +215,8 @@ class Engine:
 
     def __init__(self, device: int = 0, streams=None, flags: int = 0, mem_budget: int = 0,
                  wg_per_cu: int = 0, stage_pct: int = 0, torch_alloc: bool = True,
-                 batched: bool = False, chunk_bytes: int = 0, instance_cap: int = 0):
+                 batched: bool = False, chunk_bytes: int = 0, instance_cap: int = 0,
+                 head_ratio: int = 0, bitmap_min_run: int = 0):
         import torch  # device memory and streams come from PyTorch
 
         self._torch = torch
@@ -230,6 +233,8 @@ class Engine:
         cfg.stage_pct = stage_pct
         cfg.chunk_bytes = chunk_bytes
         cfg.instance_cap_bytes = instance_cap
+        cfg.head_ratio = head_ratio
+        cfg.bitmap_min_run = bitmap_min_run
         self._keep = []
         if torch_alloc:
             dev = torch.device("cuda", device)
@@ -545,8 +550,9 @@ class Engine:
 
     def autotune_points(self, points):
         """Run the program once per configuration point, a (wg_per_cu,
-        stage_pct, flags) triple, keep the fastest; returns (index, ms)."""
-        arr = (_TunePoint * len(points))(*[_TunePoint(w, sp, f) for w, sp, f in points])
+        stage_pct, flags[, head_ratio, bitmap_min_run]) tuple, keep the
+        fastest; returns (index, ms)."""
+        arr = (_TunePoint * len(points))(*[_TunePoint(*(tuple(p) + (0, 0))[:5]) for p in points])
         chosen, ms = ctypes.c_uint32(), ctypes.c_double()
         self._check(self._lib.wcdl_autotune_points(self._e, arr, len(points), ctypes.byref(chosen),
                                                    ctypes.byref(ms)))

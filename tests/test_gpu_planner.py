@@ -75,14 +75,17 @@ def test_planner_examines_fewer_candidates_on_a_selective_atom():
 
 
 def test_autotune_points_chooses_and_remembers():
-    """The configuration tuner runs every point (results equal the oracle's
-    whichever wins), keeps the winner, and a second engine with the same
-    program and size bucket gets the remembered choice without a run."""
+    """The configuration tuner runs every point (granularity, staging,
+    strategy flags, head-run flush ratio, run-bitmap threshold; results
+    equal the oracle's whichever wins), keeps the winner, and a second
+    engine with the same program and size bucket gets the remembered choice
+    without a run."""
     from paper_2604_20073_amd import WCDL_F_RUN_BITMAPS_OFF, WcdlError
     edges = W.er_graph(900, 4000, 85)
     rels = {"edge": 2, "path": 2, "tri": 3}
     _, expect = oracle.evaluate(rels, TC + "\n" + TRI, {"edge": edges})
-    points = [(32, 0, 0), (16, 0, WCDL_F_COST_PLANNER), (64, 50, WCDL_F_RUN_BITMAPS_OFF)]
+    points = [(32, 0, 0), (16, 0, WCDL_F_COST_PLANNER), (64, 50, WCDL_F_RUN_BITMAPS_OFF),
+              (32, 0, 0, 2, 2048), (8, 200, 0, 64, 8192)]
     engines = []
     for k in range(2):
         e = Engine()
@@ -104,3 +107,34 @@ def test_autotune_points_chooses_and_remembers():
         engines[1].autotune_points([(32, 0, 0x10)])   # batched is not a tuning flag
     for e in engines:
         e.close()
+
+
+@pytest.mark.parametrize("head_ratio,min_run", [(1, 0), (64, 0), (0, 4096)])
+def test_flush_ratio_and_bitmap_threshold_keep_results(head_ratio, min_run):
+    """The head-run flush ratio and the run-bitmap threshold change when rows
+    move and which runs get bitmaps, never the results (the long-tail
+    same-generation tree and the 4-clique rule against the oracle)."""
+    par = np.array([(0, 1)] + [(i, i + 1) for i in range(1, 400)] +
+                   [(i % 50, 400 + i) for i in range(1, 3000)], dtype=np.uint32)
+    rels = {"par": 2, "sg": 2}
+    o, expect = oracle.evaluate(rels, SAME_GEN, {"par": par})
+    e = Engine(head_ratio=head_ratio, bitmap_min_run=min_run)
+    for n, k in rels.items():
+        e.declare(n, k)
+    e.add_rules(SAME_GEN)
+    e.load("par", par)
+    e.run()
+    assert np.array_equal(e.read_numpy("sg"), expect["sg"])
+    assert e.delta_sizes("sg") == o.delta_sizes("sg")
+    e.close()
+    edges = W.rmat_graph(11, 20000, 86)
+    rels = {"edge": 2, "q": 4}
+    _, expect = oracle.evaluate(rels, Q4, {"edge": edges})
+    e = Engine(head_ratio=head_ratio, bitmap_min_run=min_run)
+    for n, k in rels.items():
+        e.declare(n, k)
+    e.add_rules(Q4)
+    e.load("edge", edges)
+    e.run()
+    assert np.array_equal(e.read_numpy("q"), expect["q"])
+    e.close()
