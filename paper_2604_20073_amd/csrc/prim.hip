@@ -800,9 +800,59 @@ void column_or(Ctx c, u32 k, const u32* const* cols, u64 n, u32* d_or) {
   WCDL_HIP(hipGetLastError());
 }
 
+// ---- small sorts -----------------------------------------------------------
+//
+// Up to SMALL_SORT rows are sorted by one workgroup in LDS: the columns are
+// loaded once, a bitonic network orders row indices by (row, index), and the
+// rows are written out in that order.  One launch instead of the radix
+// passes' four per 8-bit digit, for the small deltas of long-tail rounds.
+
+constexpr u32 SMALL_SORT = 2048;
+
+__device__ inline bool row_less(const u32* keys, u32 k, uint16_t a, uint16_t b) {
+  for (u32 j = 0; j < k; ++j) {
+    const u32 x = keys[j * SMALL_SORT + a], y = keys[j * SMALL_SORT + b];
+    if (x != y) return x < y;
+  }
+  return a < b;
+}
+
+__global__ __launch_bounds__(WG) void k_small_sort(ColsIn in, ColsOut out, u32 k, u32 n, u32 n2) {
+  extern __shared__ u32 lds[];
+  u32* keys = lds;                                             // k x SMALL_SORT
+  uint16_t* idx = reinterpret_cast<uint16_t*>(lds + k * SMALL_SORT);  // n2 (power of two)
+  for (u32 j = 0; j < k; ++j)
+    for (u32 i = threadIdx.x; i < n2; i += WG) keys[j * SMALL_SORT + i] = i < n ? in.c[j][i] : ~0u;
+  for (u32 i = threadIdx.x; i < n2; i += WG) idx[i] = (uint16_t)i;
+  __syncthreads();
+  for (u32 size = 2; size <= n2; size <<= 1)
+    for (u32 stride = size >> 1; stride > 0; stride >>= 1) {
+      for (u32 t = threadIdx.x; t < n2 / 2; t += WG) {
+        const u32 i = 2 * stride * (t / stride) + t % stride, j = i + stride;
+        const bool up = (i & size) == 0;
+        const uint16_t a = idx[i], b = idx[j];
+        if (row_less(keys, k, b, a) == up) {
+          idx[i] = b;
+          idx[j] = a;
+        }
+      }
+      __syncthreads();
+    }
+  for (u32 j = 0; j < k; ++j)
+    for (u32 i = threadIdx.x; i < n; i += WG) out.c[j][i] = keys[j * SMALL_SORT + idx[i]];
+}
+
 void radix_sort_rows(Ctx c, u32 k, const u32* const* in_cols, u32* const* out_cols, u64 n,
                      const u32* col_bits) {
   if (k == 0 || k > (u32)MAXA) throw Error(WCDL_E_UNSUPPORTED, "radix sort arity");
+  if (n > 1 && n <= SMALL_SORT) {
+    u32 n2 = 2;
+    while (n2 < n) n2 <<= 1;
+    const size_t lds = (size_t)k * SMALL_SORT * sizeof(u32) + (size_t)n2 * sizeof(uint16_t);
+    k_small_sort<<<1, WG, lds, c.s>>>(cols_in(k, in_cols), cols_out(k, out_cols), k, (u32)n, n2);
+    WCDL_HIP(hipGetLastError());
+    return;
+  }
   // Digit passes from the least significant digit of the last column up.
   std::vector<std::pair<u32, u32>> passes;  // (column, shift)
   for (int j = (int)k - 1; j >= 0; --j)

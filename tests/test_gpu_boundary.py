@@ -269,3 +269,22 @@ def test_trim_returns_cached_blocks_and_keeps_relations():
     e.run()
     assert np.array_equal(e.read_numpy("path"), expect["path"])
     e.close()
+
+
+@pytest.mark.parametrize("arity", [1, 2, 3, 6])
+def test_loaded_relations_sorted_and_deduplicated_at_every_size(arity):
+    """Loading sorts and deduplicates: inputs on both sides of the
+    one-workgroup sort's limit (2,048 rows), with repeats, zeros and the
+    largest value, read back equal to numpy's sorted unique rows."""
+    g = np.random.default_rng(95 + arity)
+    e = Engine()
+    e.declare("r", arity)
+    for n in (2, 3, 17, 1000, 2047, 2048, 2049, 5000):
+        rows = g.choice(np.array([0, 1, 7, 2**31, 2**32 - 1, 123456], dtype=np.uint32),
+                        size=(n, arity)).astype(np.uint32)
+        rows[: n // 3] = g.integers(0, 2**32, size=(n // 3, arity), dtype=np.uint64).astype(np.uint32)
+        e.clear("r")
+        e.load("r", rows)
+        e.run()
+        assert np.array_equal(e.read_numpy("r"), np.unique(rows, axis=0)), n
+    e.close()
