@@ -69,6 +69,18 @@ def profiled_traffic(kernel: str, workload: str):
     return int(rec["traffic_bytes_per_launch"])
 
 
+def host_cpu_model() -> str:
+    """The host CPU's model name (first processor entry), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(edges: np.ndarray, target_s: float, threads: int):
     """The CPU oracle on a bounded sample: the same two rules with the
     outermost atom restricted to the edges of a random sample of source
@@ -105,6 +117,7 @@ def cpu_baseline(edges: np.ndarray, target_s: float, threads: int):
             break
         frac = min(1.0, frac * max(2.0, min(8.0, target_s / max(secs, 1e-3))))
     base, sources, o = last
+    base["cpu"] = host_cpu_model()
     return base, sources, o.read("tri"), o.read("q")
 
 

@@ -339,6 +339,7 @@ struct wcdl_engine {
   // Cost planner: distinct values per column of each relation, with the row
   // count they were taken at (recomputed when it changes).
   std::map<uint32_t, std::pair<uint64_t, std::vector<uint64_t>>> col_stats;
+  uint64_t device_total = 0;  // bytes of device memory (queried once)
 };
 
 // An instance of a batched engine's program: its rows carry `id` in the
@@ -1590,11 +1591,9 @@ void eval_batch(Engine* e, std::vector<Version>& vs, Stats& st, const Sink& sink
       stage_plan[&R] = bytes;
       want_total += bytes;
     }
-    size_t free_b = 0, total_b = 0;
-    WCDL_HIP(hipMemGetInfo(&free_b, &total_b));
     // With a memory budget the arena shares what the relations leave of it.
     const u64 held = resident_bytes(e), budget = e->cfg.mem_budget_bytes;
-    const u64 limit = budget ? (budget > held ? (budget - held) / 2 : 0) : (u64)(total_b * 0.2);
+    const u64 limit = budget ? (budget > held ? (budget - held) / 2 : 0) : (u64)(e->device_total * 0.2);
     const double scale = want_total > limit ? (double)limit / (double)want_total : 1.0;
     for (auto& kv : stage_plan) {
       const u64 per_chunk = STAGE_CHUNK * kv.first->v->plan.head_arity * 4ull;
@@ -2716,6 +2715,9 @@ wcdl_status wcdl_create(const wcdl_config* cfg, wcdl_engine** out) {
     e->cfg.streams = nullptr;
     e->mem.reset(new DeviceMemory(e->cfg.alloc, e->streams[0]));
     ensure_scratch_address(e->cfg.device);
+    size_t free_b = 0, total_b = 0;
+    WCDL_HIP(hipMemGetInfo(&free_b, &total_b));
+    e->device_total = total_b;
   });
   if (st != WCDL_OK) {
     std::fprintf(stderr, "wcdl_create: %s\n", e->err.c_str());
