@@ -150,6 +150,9 @@ typedef struct {
                                 WCDL_E_BUDGET before anything of that round is
                                 written: the relations keep the last completed
                                 round and the engine stays usable.  The count
+                                kernels stop as soon as the rows found so far
+                                cross the bound, so a round far over it fails
+                                quickly.  The count
                                 pass's staging arena is also held within the
                                 bound.  Kernel scratch (sort buffers, histograms,
                                 root keys) is not counted. */

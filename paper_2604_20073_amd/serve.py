@@ -222,8 +222,8 @@ class Server:
             except WcdlError as x:
                 if x.code != -8:
                     raise
-                # The step's count passes do not fit the pool: send back the
-                # newer half of this step's admissions (or the newest request
+                # The step's count passes do not fit the pool: set aside the
+                # newer half of this step's admissions (or the newest quarter
                 # in flight) and run the step again.
                 if recent:
                     back = recent[len(recent) // 2:]
