@@ -88,6 +88,11 @@ typedef int32_t wcdl_status;
                                     of all but its last column (Sec. 4, Compute
                                     Delta: the grouped sort orders and dedups
                                     such chunks one LDS tile of groups at a time) */
+#define WCDL_F_TILE_DEDUP_OFF 0x800u /* sort large unordered candidate sets with
+                                    the radix passes directly, without first
+                                    dropping rows repeated inside tiles of
+                                    2,048 consecutive rows (Sec. 4, Compute
+                                    Delta) */
 #define WCDL_F_CHECKED 0x200u    /* checked mode: after every merge the engine
                                     verifies on the device that each stored copy
                                     of the relation is sorted without repeats and
@@ -403,7 +408,8 @@ wcdl_status wcdl_trim(wcdl_engine* e, uint64_t* released);
 /* Strategy flags the configuration tuner may set or clear. */
 #define WCDL_TUNE_FLAGS (WCDL_F_STREAMS_OFF | WCDL_F_XPROD_OFF | WCDL_F_STAGE_OFF | \
                          WCDL_F_HEAD_BODY_OFF | WCDL_F_RUN_BITMAPS_OFF |            \
-                         WCDL_F_GROUPED_SORT_OFF | WCDL_F_COST_PLANNER)
+                         WCDL_F_GROUPED_SORT_OFF | WCDL_F_COST_PLANNER |           \
+                         WCDL_F_TILE_DEDUP_OFF)
 
 /* One configuration for wcdl_autotune_points: the partition granularity, the
  * count-pass staging arena size (0 = default), the strategy flags (only bits

@@ -1967,6 +1967,20 @@ Cols sort_unique(Engine* e, Cols rows, u32 grouped) {
       if (sort_unique_grouped(c, k, in.data(), rows.n, zbits, op.data(), &out.n)) return out;
     }
   }
+  if (rows.n >= (1u << 20) && k <= 4 && !(e->cfg.flags & WCDL_F_TILE_DEDUP_OFF)) {
+    // Repeats emitted close together go before the radix passes.
+    Ctx c = ctx(e);
+    Cols fewer;
+    fewer.order = rows.order;
+    std::vector<u32*> op;
+    for (u32 j = 0; j < k; ++j) {
+      fewer.col.emplace_back(c.mem, rows.n);
+      op.push_back(fewer.col.back().get());
+    }
+    std::vector<const u32*> in(rows.ptrs());
+    fewer.n = drop_tile_repeats(c, k, in.data(), rows.n, op.data());
+    rows = std::move(fewer);
+  }
   Cols srt = sort_rows(e, 0, rows.order, std::vector<const u32*>(rows.ptrs()), rows.n, true);
   rows = Cols();
   return srt;

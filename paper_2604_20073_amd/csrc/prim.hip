@@ -737,6 +737,68 @@ u64 compact_flagged(Ctx c, u32 k, const ColsIn& a, u64 n, const u32* flags, cons
   return h;
 }
 
+// ---- repeats inside tiles ----------------------------------------------------
+//
+// A join emits the repeats of a row close together when the same binding is
+// reached through several values of a projected-away variable.  Ahead of a
+// full sort, each workgroup keeps one copy of every row repeated inside its
+// tile of TILE_DEDUP consecutive rows: the tile goes to LDS, each row claims
+// a slot of an LDS hash set by compare-and-swap of its index (linear
+// probing over twice as many slots as rows, so every probe ends), and a row
+// that meets an equal row in the set is dropped.
+
+constexpr u32 TILE_DEDUP = 2048;
+constexpr u32 TILE_DEDUP_SLOTS = 2 * TILE_DEDUP;
+
+__global__ __launch_bounds__(WG) void k_tile_first(ColsIn in, u32 k, u64 n, u32* keep) {
+  extern __shared__ u32 lds[];
+  u32* rows = lds;                          // k x TILE_DEDUP
+  u32* table = lds + k * TILE_DEDUP;        // TILE_DEDUP_SLOTS row indices, ~0u = empty
+  const u64 base = (u64)blockIdx.x * TILE_DEDUP;
+  const u32 m = (u32)(n - base < TILE_DEDUP ? n - base : TILE_DEDUP);
+  for (u32 j = 0; j < k; ++j)
+    for (u32 i = threadIdx.x; i < m; i += WG) rows[j * TILE_DEDUP + i] = in.c[j][base + i];
+  for (u32 t = threadIdx.x; t < TILE_DEDUP_SLOTS; t += WG) table[t] = ~0u;
+  __syncthreads();
+  for (u32 i = threadIdx.x; i < m; i += WG) {
+    u32 h = 0x9e3779b9u;
+    for (u32 j = 0; j < k; ++j) {
+      h = (h ^ rows[j * TILE_DEDUP + i]) * 0x85ebca6bu;
+      h ^= h >> 13;
+    }
+    u32 slot = h & (TILE_DEDUP_SLOTS - 1);
+    u32 first = 1, open = 1;
+    while (open) {
+      const u32 prev = atomicCAS(&table[slot], ~0u, i);
+      if (prev == ~0u) {
+        open = 0;  // this row holds the slot
+      } else {
+        u32 same = 1;
+        for (u32 j = 0; j < k; ++j) same &= rows[j * TILE_DEDUP + prev] == rows[j * TILE_DEDUP + i] ? 1u : 0u;
+        if (same) {
+          first = 0;
+          open = 0;
+        } else {
+          slot = (slot + 1) & (TILE_DEDUP_SLOTS - 1);
+        }
+      }
+    }
+    keep[base + i] = first;
+  }
+}
+
+u64 drop_tile_repeats(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32* const* out_cols) {
+  if (k == 0 || k > 4) throw Error(WCDL_E_UNSUPPORTED, "tile deduplication arity");
+  if (n == 0) return 0;
+  DBuf<u32> keep(c.mem, n);
+  const u64 tiles = ceil_div(n, (u64)TILE_DEDUP);
+  const size_t lds = ((size_t)k * TILE_DEDUP + TILE_DEDUP_SLOTS) * sizeof(u32);
+  const ColsIn a = cols_in(k, in_cols);
+  k_tile_first<<<(u32)tiles, WG, lds, c.s>>>(a, k, n, keep.get());
+  WCDL_HIP(hipGetLastError());
+  return compact_flagged(c, k, a, n, keep.get(), cols_out(k, out_cols));
+}
+
 u64 select_leading(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32 lead_col, const u32* ids,
                    u64 nids, bool keep_listed, u32* const* out_cols) {
   if (n == 0) return 0;

@@ -308,6 +308,10 @@ bool sort_unique_grouped(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32 zbi
                          u32* const* out_cols, u64* out_n);
 // Unique adjacent rows of a sorted input; returns the count (synchronises).
 u64 unique_rows(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32* const* out_cols);
+// One copy of every row repeated inside each tile of 2,048 consecutive rows,
+// in order (rows repeated across tiles stay); returns the rows written
+// (synchronises).  Arity at most 4.
+u64 drop_tile_repeats(Ctx c, u32 k, const u32* const* in_cols, u64 n, u32* const* out_cols);
 // Rows of sorted-unique A absent from sorted-unique B and from the optional
 // sorted-unique B2; returns count (syncs).
 u64 set_difference(Ctx c, u32 k, const u32* const* a, u64 na, const u32* const* b, u64 nb,

@@ -34,6 +34,7 @@ WCDL_F_RUN_BITMAPS_OFF = 0x40
 WCDL_F_GROUPED_SORT_OFF = 0x80
 WCDL_F_CHECKED = 0x200
 WCDL_F_COST_PLANNER = 0x400
+WCDL_F_TILE_DEDUP_OFF = 0x800
 PHASES = ["histogram", "count", "materialize", "delta", "index", "merge", "load", "other"]
 KERNELS = ["join_count", "join_materialize", "join_histogram", "unused"]
 ERRORS = {-1: "E_INVALID", -2: "E_ARITY", -3: "E_UNKNOWN_REL", -4: "E_UNSAFE_RULE",

@@ -288,3 +288,24 @@ def test_loaded_relations_sorted_and_deduplicated_at_every_size(arity):
         e.run()
         assert np.array_equal(e.read_numpy("r"), np.unique(rows, axis=0)), n
     e.close()
+
+
+@pytest.mark.parametrize("flags", [0, 0x800], ids=["tile_dedup", "tile_dedup_off"])
+def test_reversed_two_paths_large_unordered_candidates(flags):
+    """r(y,x) :- e(x,z), e(z,y) on a skewed graph: millions of candidate rows
+    per chunk, not in head order and full of repeats (one per middle vertex
+    z), so Compute Delta takes the radix path, with and without the tile
+    repeat filter ahead of it; both equal the oracle."""
+    edges = W.rmat_graph(12, 60000, 96)
+    rules = "r(y,x) :- e(x,z), e(z,y)."
+    rels = {"e": 2, "r": 2}
+    _, expect = oracle.evaluate(rels, rules, {"e": edges})
+    e = Engine(flags=flags)
+    for n, k in rels.items():
+        e.declare(n, k)
+    e.add_rules(rules)
+    e.load("e", edges)
+    st = e.run()
+    assert st["candidate_rows"] > (1 << 21) and st["candidate_rows"] > 2 * len(expect["r"])
+    assert np.array_equal(e.read_numpy("r"), expect["r"])
+    e.close()
