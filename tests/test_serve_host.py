@@ -15,6 +15,8 @@ from paper_2604_20073_amd.engine import WcdlError
 
 
 class FakeEngine:
+    nomem_once = False   # plain mode: the next run fails once for want of device memory
+
     """Instances with a fixed number of rounds (1 + id % 4).  Each step
     reports the bytes a count pass would reserve (10 output rows per input
     row of every live instance, at the output relation's stored arity) and
@@ -101,6 +103,9 @@ class FakeEngine:
         self.loaded += len(rows)
 
     def run(self):
+        if FakeEngine.nomem_once:
+            FakeEngine.nomem_once = False
+            raise WcdlError(-7, "device allocation failed")
         if self.budget and self.loaded * 3 * 8 > self.budget:
             raise WcdlError(-8, "over budget")
         return {}
@@ -112,6 +117,7 @@ class FakeEngine:
         return np.zeros((3 * self.loaded, 2), np.uint32)
 
     def trim(self):
+        self.trims = getattr(self, "trims", 0) + 1
         return 0
 
     def serve_rejected(self):
@@ -274,3 +280,15 @@ def test_large_requests_run_alone_between_steps(fake):
     assert out["rows"][1]["path"].shape == (900, 2)
     batched = fake[0]
     assert sorted(set(batched.released)) == [0, 2, 4]     # only the small ones shared steps
+
+
+def test_plain_replay_retries_once_after_trimming(fake):
+    """replay_plain: a run out of device memory is run again after every
+    engine returns its cached scratch; over-budget runs are rejected."""
+    trace, facts = trace_of([5, 20000, 7], kinds=["tc", "tc", "tri"])
+    FakeEngine.nomem_once = True
+    out = serve.replay_plain(trace, facts, instance_cap_bytes=100_000)
+    assert out["completed"] == 2 and out["rejected"] == 1
+    assert out["sizes"][0] == {"path": 15} and out["sizes"][2] == {"tri": 21}
+    assert all(getattr(e, "trims", 0) == 1 for e in fake)   # every engine trimmed once
+    assert not FakeEngine.nomem_once
